@@ -1,0 +1,217 @@
+/*
+ * fsmmc.h -- C ABI of libfsmmc: FSM-scheduled multi-chain MCMC on AMD
+ * MI355X (gfx950).
+ *
+ * The calls follow the paper's statement of the problem (Dance et al.,
+ * "Efficiently Vectorized MCMC on Modern Accelerators", ICML 2025):
+ *   - a sampler is a map sample: R^d x N -> R^d x N from a state and a
+ *     random state to the next state (Sec. 2.1); m chains are the batched
+ *     map R^{d x m} x N^m -> R^{d x m} x N^m;
+ *   - the FSM runtime advances every chain by FSM steps and collects a draw
+ *     whenever a chain passes its final state (Sec. 3.2, Alg. "step function
+ *     for FSM", Alg. "FSM MCMC algorithm"; Appendix, Alg. "Vectorized FSM
+ *     MCMC algorithm");
+ *   - the synchronized runtime draws sample i of every chain before any
+ *     chain starts sample i+1 (Appendix, Alg. "Vectorized MCMC algorithm
+ *     with vmap(sample)"; Sec. 2.2).
+ *
+ * Conventions for every call:
+ *   - Pointers named "device" are HIP device pointers on the context's
+ *     device; "host" pointers are ordinary CPU memory.
+ *   - Arrays are dense, row-major, in the job's dtype (FP32 or FP64) unless
+ *     stated otherwise.
+ *   - Calls return FSMMC_OK or an error code; no exception crosses the ABI.
+ *     After an error the message is in fsmmc_last_error() (per thread) and
+ *     the job is unchanged unless the text says otherwise.
+ *   - Work is queued on the job's stream; a call returns before the device
+ *     finishes unless it reports completion (an all_done out-argument) or
+ *     says it synchronises.
+ *   - Given (target, sampler, seed, x0), the draws are bit-identical whether
+ *     produced by fsmmc_step_fsm or fsmmc_step_synchronized, for any split of
+ *     the work into calls and for any launch tuning.
+ */
+#ifndef FSMMC_H
+#define FSMMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FSMMC_OK = 0,
+    FSMMC_EINVAL = 1,   /* bad argument: null pointer, size, kind or dtype        */
+    FSMMC_ENOMEM = 2,   /* device allocation failed                               */
+    FSMMC_EBUDGET = 3,  /* the job would exceed the context's HBM budget          */
+    FSMMC_EDEVICE = 4,  /* a HIP runtime call failed                              */
+    FSMMC_EBUSY = 5,    /* the request conflicts with work in flight              */
+    FSMMC_ENOTDONE = 6, /* the requested draws are not produced yet               */
+    FSMMC_ENOTSUP = 7   /* valid request this build does not implement            */
+} fsmmc_status;
+
+/* Targets: the density each chain samples. */
+typedef enum {
+    FSMMC_GP_GAUSS = 0,    /* latent GP, prior N(0, L L^T), y_i ~ N(f_i, noise_sd^2) */
+    FSMMC_GP_LOGISTIC = 1, /* latent GP, prior N(0, L L^T), y_i ~ Bern(sigmoid f_i)   */
+    FSMMC_LOGREG = 2,      /* Bayesian logistic regression, prior N(0, I)            */
+    FSMMC_FUNNEL = 3,      /* Neal's funnel: v ~ N(0, 9), x_i | v ~ N(0, e^v)        */
+    FSMMC_GAUSS_DIAG = 4   /* N(0, diag(prec)^-1)                                    */
+} fsmmc_target_kind;
+
+/* Samplers (Sec. 3.1, Fig. "Finite state machines for the sample function"). */
+typedef enum {
+    FSMMC_ESS = 0,  /* elliptical slice sampling: INIT, SHRINK, DONE                  */
+    FSMMC_NUTS = 1, /* no-U-turn HMC: INIT, DOUBLE, INTEGRATE, CHECK, DONE            */
+    FSMMC_DRMH = 2  /* delayed-rejection MH: INIT, PROPOSE, DONE                      */
+} fsmmc_sampler_kind;
+
+typedef enum { FSMMC_F32 = 0, FSMMC_F64 = 1 } fsmmc_dtype;
+
+/* Synchronized runtime flavours. */
+typedef enum {
+    FSMMC_SYNC_VMAP = 0,   /* every chain runs max_j N_j loop bodies per draw; the
+                              bodies after a chain's own exit are computed and
+                              discarded, as a batched while loop does (Sec. 2.2)  */
+    FSMMC_SYNC_COMPACT = 1 /* finished chains idle until the draw's barrier        */
+} fsmmc_sync_mode;
+
+/* Target description.  All arrays are device pointers in the sampler's dtype;
+ * init_chains copies what it needs, so the caller may free them afterwards. */
+typedef struct {
+    int32_t kind;     /* fsmmc_target_kind                                         */
+    int32_t dim;      /* d >= 1                                                    */
+    int32_t n_data;   /* LOGREG: number of rows of X                               */
+    int32_t reserved; /* must be 0                                                 */
+    const void* X;    /* LOGREG: n_data x dim design matrix                        */
+    const void* y;    /* GP: dim observations (GAUSS) or labels in {0,1} (LOGISTIC);
+                         LOGREG: n_data labels in {0,1}                            */
+    const void* chol_L; /* GP: dim x dim lower Cholesky factor of the prior covariance
+                           (entries above the diagonal are ignored)                */
+    const void* prec; /* GAUSS_DIAG: dim precisions                                */
+    double noise_sd;  /* GP_GAUSS: observation noise standard deviation            */
+} fsmmc_target_spec;
+
+/* Sampler description. */
+typedef struct {
+    int32_t kind;      /* fsmmc_sampler_kind                                        */
+    int32_t dtype;     /* fsmmc_dtype                                               */
+    int32_t max_depth; /* NUTS: maximum tree depth J in [1, 15] (<= 2^J - 1 leapfrogs) */
+    int32_t n_stages;  /* DRMH: number of proposal stages in [1, 3]                 */
+    double step_size;  /* NUTS: leapfrog step size > 0                              */
+    double scales[4];  /* DRMH: proposal standard deviation of each stage > 0       */
+} fsmmc_sampler_spec;
+
+/* Launch tuning (0 = library default).  Tuning never changes the draws. */
+typedef struct {
+    int32_t window;        /* ESS: draws of ellipse directions precomputed per chain */
+    int32_t timing;        /* 1: time every kernel launch with HIP events on the job's
+                              stream (reported by fsmmc_job_stats)                   */
+    int32_t reserved[6];
+} fsmmc_tune;
+
+typedef struct {
+    int64_t steps;        /* FSM steps executed, summed over chains (one step = one
+                             evaluation of the expensive quantity g: a log-likelihood,
+                             a gradient or a density)                               */
+    int64_t padded_steps; /* loop bodies executed and discarded (SYNC_VMAP only)    */
+    int64_t draws;        /* draws produced, summed over chains                     */
+    int32_t chains_done;  /* chains with all n_draws draws                          */
+    int32_t guard_trips;  /* ESS draws stopped by the evaluation guard (expected 0) */
+    int32_t launches;     /* kernel launches issued for this job                    */
+    int32_t reserved;
+    /* With tune.timing = 1: device time (ms) and launch count per kernel class:
+     * [0] batched g (ESS ellipse GEMM, NUTS gradient), [1] FSM transition
+     * kernels, [2] synchronized-runtime kernels, [3] padding kernels.        */
+    double kernel_ms[4];
+    int32_t kernel_launches[4];
+} fsmmc_stats;
+
+typedef struct fsmmc_ctx fsmmc_ctx;
+typedef struct fsmmc_job fsmmc_job;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
+ * device memory all of its jobs may hold (0 = no bound).  *out receives the
+ * context.  Errors: EINVAL (null out, bad device), EDEVICE. */
+fsmmc_status fsmmc_ctx_create(int device, size_t hbm_budget_bytes, fsmmc_ctx** out);
+
+/* Destroy a context; every job of it must have been freed (else EBUSY). */
+fsmmc_status fsmmc_ctx_destroy(fsmmc_ctx* ctx);
+
+/* Bytes of device memory the context's jobs hold now. */
+size_t fsmmc_ctx_bytes_in_use(const fsmmc_ctx* ctx);
+
+/* Create a job of n_chains chains that will each produce n_draws draws, and
+ * initialise every chain (Alg. "FSM MCMC algorithm", initialisation: z =
+ * init(x0), t = 0, k = S_1).
+ *   x0:          device, n_chains x dim initial states, or NULL for the default
+ *                start (ESS: a prior draw L z; DRMH on FUNNEL: an exact funnel
+ *                draw; otherwise a standard normal draw), keyed by seed.
+ *   out_samples: device, n_chains x n_draws x dim buffer the draws are written
+ *                to (caller-owned, must outlive the job), or NULL to let the
+ *                library allocate it (counted against the budget).
+ *   stream:      hipStream_t the job's work is queued on (NULL = default stream).
+ *   tune:        launch tuning or NULL.
+ * Chain j's random stream is keyed by (seed, j) only.  The call queues the
+ * initialisation and returns.  Errors: EINVAL, ENOMEM, EBUDGET, EDEVICE, ENOTSUP. */
+fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
+                               const fsmmc_sampler_spec* sampler, int32_t n_chains,
+                               int32_t n_draws, uint64_t seed, const void* x0,
+                               void* out_samples, void* stream, const fsmmc_tune* tune,
+                               fsmmc_job** out);
+
+/* Advance every unfinished chain by FSM steps (Alg. "Vectorized FSM MCMC
+ * algorithm").  A chain stops when it holds n_draws draws or has taken
+ * max_steps steps in this call; max_steps <= 0 means run every chain to
+ * n_draws.  Each step runs the chain's cheap states back to back until the
+ * next evaluation of g and then evaluates g once (Appendix, Alg. "bundled
+ * step as input to amortized step"); chains never wait for each other inside
+ * the call.  Synchronises the job's stream before returning.  If all_done is
+ * not NULL it receives 1 when every chain has n_draws draws, else 0. */
+fsmmc_status fsmmc_step_fsm(fsmmc_job* job, int64_t max_steps, int32_t* all_done);
+
+/* Produce the next n_draws draws of every chain in lock step: draw i of all
+ * chains completes before any chain starts draw i+1 (Appendix, Alg.
+ * "Vectorized MCMC algorithm with vmap(sample)").  mode is an
+ * fsmmc_sync_mode.  All chains must be at the same draw index and at a draw
+ * boundary (EINVAL otherwise).  Synchronises the job's stream.  all_done as
+ * for fsmmc_step_fsm. */
+fsmmc_status fsmmc_step_synchronized(fsmmc_job* job, int32_t n_draws, int32_t mode,
+                                     int32_t* all_done);
+
+/* Copy draws [draw_begin, draw_end) of every chain to dst, laid out
+ * n_chains x (draw_end - draw_begin) x dim; dst is host memory if dst_is_host
+ * is non-zero, else device memory.  Synchronises the job's stream.  Errors:
+ * EINVAL (range), ENOTDONE (a chain has not produced draw_end - 1 yet). */
+fsmmc_status fsmmc_collect_samples(fsmmc_job* job, int32_t draw_begin, int32_t draw_end,
+                                   void* dst, int32_t dst_is_host);
+
+/* Copy the per-draw loop counts N_ij (ESS: log-likelihood evaluations; NUTS:
+ * leapfrog steps; DRMH: stages) to host memory dst, n_chains x n_draws int32
+ * (Sec. 2.2, "Formalizing the problem").  Synchronises the job's stream. */
+fsmmc_status fsmmc_collect_counts(fsmmc_job* job, int32_t* dst);
+
+/* Per-chain draw counters t_j (host dst, n_chains uint32).  Synchronises. */
+fsmmc_status fsmmc_chain_progress(fsmmc_job* job, uint32_t* dst);
+
+/* Counters of the job so far.  Synchronises the job's stream. */
+fsmmc_status fsmmc_job_stats(fsmmc_job* job, fsmmc_stats* out);
+
+/* Block until the job's queued work has finished. */
+fsmmc_status fsmmc_job_sync(fsmmc_job* job);
+
+/* Release a job and its device memory (waits for its queued work first). */
+fsmmc_status fsmmc_job_free(fsmmc_job* job);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* fsmmc_last_error(void);
+
+/* Library version string. */
+const char* fsmmc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSMMC_H */

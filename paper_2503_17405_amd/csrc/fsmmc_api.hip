@@ -1,0 +1,512 @@
+// fsmmc_api.hip -- the C ABI declared in include/fsmmc.h: contexts, jobs,
+// the FSM runtime loop and the synchronized runtime loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fsmmc_internal.h"
+
+using namespace fsmmc;
+
+namespace {
+thread_local std::string g_err;
+
+fsmmc_status fail(fsmmc_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+fsmmc_status hip_fail(hipError_t e, const char* what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return FSMMC_EDEVICE;
+}
+
+#define HIP_TRY(expr)                                          \
+    do {                                                       \
+        hipError_t e__ = (expr);                               \
+        if (e__ != hipSuccess) return hip_fail(e__, #expr);    \
+    } while (0)
+
+__global__ void fill_i64_kernel(int64_t* p, int64_t v, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int32_t v, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+}  // namespace
+
+struct fsmmc_ctx {
+    int device = 0;
+    size_t budget = 0;
+    std::atomic<size_t> used{0};
+    std::atomic<int> jobs{0};
+};
+
+struct TimedLaunch {
+    hipEvent_t a, b;
+    int cls;
+};
+
+struct fsmmc_job {
+    fsmmc_ctx* ctx = nullptr;
+    hipStream_t stream = nullptr;
+    JobDev d;
+    std::vector<void*> allocs;
+    size_t bytes = 0;
+    unsigned long long* h_ctr = nullptr;  // pinned mirror of d.ctr
+    int launches = 0;
+    // optional per-launch device timing
+    bool timing = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<TimedLaunch> pending;
+    double kms[4] = {0, 0, 0, 0};
+    int klaunch[4] = {0, 0, 0, 0};
+};
+
+// Kernel classes of fsmmc_stats.kernel_ms.
+enum { KC_G = 0, KC_FSM = 1, KC_SYNC = 2, KC_PAD = 3 };
+
+static hipEvent_t ev_get(fsmmc_job* j)
+{
+    hipEvent_t e = nullptr;
+    if (!j->pool.empty()) {
+        e = j->pool.back();
+        j->pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+    }
+    return e;
+}
+
+// Queue one launcher call; with timing on, bracket it with events.
+template <typename F>
+static hipError_t launch(fsmmc_job* j, int cls, F&& fn)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (j->timing) {
+        a = ev_get(j);
+        if (a) (void)hipEventRecord(a, j->stream);
+    }
+    hipError_t e = fn();
+    j->launches++;
+    if (j->timing && a) {
+        b = ev_get(j);
+        if (b) {
+            (void)hipEventRecord(b, j->stream);
+            j->pending.push_back({a, b, cls});
+        } else {
+            j->pool.push_back(a);
+        }
+    }
+    return e;
+}
+
+// After the stream has drained: fold the recorded intervals into the totals.
+static void harvest(fsmmc_job* j)
+{
+    for (const TimedLaunch& t : j->pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+            j->kms[t.cls] += ms;
+            j->klaunch[t.cls]++;
+        }
+        j->pool.push_back(t.a);
+        j->pool.push_back(t.b);
+    }
+    j->pending.clear();
+}
+
+static fsmmc_status job_alloc(fsmmc_job* j, size_t bytes, void** p)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    fsmmc_ctx* c = j->ctx;
+    if (c->budget) {
+        size_t now = c->used.fetch_add(bytes) + bytes;
+        if (now > c->budget) {
+            c->used.fetch_sub(bytes);
+            return fail(FSMMC_EBUDGET, "job exceeds the context's HBM budget");
+        }
+    } else {
+        c->used.fetch_add(bytes);
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        c->used.fetch_sub(bytes);
+        *p = nullptr;
+        return fail(FSMMC_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    j->allocs.push_back(*p);
+    j->bytes += bytes;
+    e = hipMemsetAsync(*p, 0, bytes, j->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+    return FSMMC_OK;
+}
+
+static void job_release(fsmmc_job* j)
+{
+    if (!j) return;
+    if (j->stream) (void)hipStreamSynchronize(j->stream);
+    for (void* p : j->allocs) (void)hipFree(p);
+    if (j->h_ctr) (void)hipHostFree(j->h_ctr);
+    for (const TimedLaunch& t : j->pending) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (hipEvent_t e : j->pool) (void)hipEventDestroy(e);
+    if (j->ctx) {
+        j->ctx->used.fetch_sub(j->bytes);
+        j->ctx->jobs.fetch_sub(1);
+    }
+    delete j;
+}
+
+#define ALLOC(ptr, bytes)                                               \
+    do {                                                                \
+        void* p__ = nullptr;                                            \
+        fsmmc_status s__ = job_alloc(job, (bytes), &p__);               \
+        if (s__ != FSMMC_OK) {                                          \
+            job_release(job);                                           \
+            return s__;                                                 \
+        }                                                               \
+        ptr = reinterpret_cast<decltype(ptr)>(p__);                     \
+    } while (0)
+
+#define HIP_TRY_JOB(expr)                                               \
+    do {                                                                \
+        hipError_t e__ = (expr);                                        \
+        if (e__ != hipSuccess) {                                        \
+            fsmmc_status s__ = hip_fail(e__, #expr);                    \
+            job_release(job);                                           \
+            return s__;                                                 \
+        }                                                               \
+    } while (0)
+
+extern "C" {
+
+const char* fsmmc_last_error(void) { return g_err.c_str(); }
+
+const char* fsmmc_version(void) { return "fsmmc 0.1 (gfx950)"; }
+
+fsmmc_status fsmmc_ctx_create(int device, size_t hbm_budget_bytes, fsmmc_ctx** out)
+{
+    if (!out) return fail(FSMMC_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(FSMMC_EINVAL, "no such device");
+    HIP_TRY(hipSetDevice(device));
+    fsmmc_ctx* c = new fsmmc_ctx();
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    *out = c;
+    return FSMMC_OK;
+}
+
+fsmmc_status fsmmc_ctx_destroy(fsmmc_ctx* ctx)
+{
+    if (!ctx) return fail(FSMMC_EINVAL, "ctx is NULL");
+    if (ctx->jobs.load() != 0) return fail(FSMMC_EBUSY, "context still has jobs");
+    delete ctx;
+    return FSMMC_OK;
+}
+
+size_t fsmmc_ctx_bytes_in_use(const fsmmc_ctx* ctx) { return ctx ? ctx->used.load() : 0; }
+
+static fsmmc_status validate(const fsmmc_target_spec* t, const fsmmc_sampler_spec* s, int32_t m,
+                             int32_t n)
+{
+    if (!t || !s) return fail(FSMMC_EINVAL, "target or sampler spec is NULL");
+    if (m < 1) return fail(FSMMC_EINVAL, "n_chains must be >= 1");
+    if (n < 1) return fail(FSMMC_EINVAL, "n_draws must be >= 1");
+    if (t->dim < 1) return fail(FSMMC_EINVAL, "dim must be >= 1");
+    if (t->reserved != 0) return fail(FSMMC_EINVAL, "reserved field must be 0");
+    if (s->dtype != FSMMC_F32 && s->dtype != FSMMC_F64) return fail(FSMMC_EINVAL, "bad dtype");
+    if ((int64_t)m * (int64_t)n > (int64_t)1 << 31) return fail(FSMMC_EINVAL, "n_chains * n_draws too large");
+    if (s->kind == FSMMC_ESS) {
+        if (t->kind != FSMMC_GP_GAUSS && t->kind != FSMMC_GP_LOGISTIC)
+            return fail(FSMMC_EINVAL, "ESS needs a GP target");
+        if (!t->chol_L || !t->y) return fail(FSMMC_EINVAL, "GP target needs chol_L and y");
+        if (t->kind == FSMMC_GP_GAUSS && !(t->noise_sd > 0.0))
+            return fail(FSMMC_EINVAL, "GP_GAUSS needs noise_sd > 0");
+        if (!ess_supported_epl(t->dim, s->dtype))
+            return fail(FSMMC_ENOTSUP, "dim too large for this dtype");
+        return FSMMC_OK;
+    }
+    if (s->kind == FSMMC_NUTS || s->kind == FSMMC_DRMH)
+        return fail(FSMMC_ENOTSUP, "sampler not built into this library version");
+    return fail(FSMMC_EINVAL, "unknown sampler kind");
+}
+
+// Copy a dim x dim matrix (device, row-major) into a zero-padded Dp x Dp
+// lower-triangular device buffer (entries above the diagonal dropped).
+static fsmmc_status stage_lower(fsmmc_job* job, const void* src, int D, int Dp, size_t es, void* dst)
+{
+    std::vector<unsigned char> h((size_t)D * D * es), p((size_t)Dp * Dp * es, 0);
+    HIP_TRY(hipMemcpy(h.data(), src, h.size(), hipMemcpyDeviceToHost));
+    for (int r = 0; r < D; ++r) std::memcpy(&p[(size_t)r * Dp * es], &h[(size_t)r * D * es], (size_t)(r + 1) * es);
+    HIP_TRY(hipMemcpyAsync(dst, p.data(), p.size(), hipMemcpyHostToDevice, job->stream));
+    HIP_TRY(hipStreamSynchronize(job->stream));
+    return FSMMC_OK;
+}
+
+fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
+                               const fsmmc_sampler_spec* sampler, int32_t n_chains, int32_t n_draws,
+                               uint64_t seed, const void* x0, void* out_samples, void* stream,
+                               const fsmmc_tune* tune, fsmmc_job** out)
+{
+    if (!ctx) return fail(FSMMC_EINVAL, "ctx is NULL");
+    if (!out) return fail(FSMMC_EINVAL, "out is NULL");
+    *out = nullptr;
+    fsmmc_status st = validate(target, sampler, n_chains, n_draws);
+    if (st != FSMMC_OK) return st;
+    HIP_TRY(hipSetDevice(ctx->device));
+
+    fsmmc_job* job = new fsmmc_job();
+    job->ctx = ctx;
+    job->timing = tune && tune->timing;
+    ctx->jobs.fetch_add(1);
+    job->stream = (hipStream_t)stream;
+    JobDev& d = job->d;
+    d.kind = sampler->kind;
+    d.target = target->kind;
+    d.dtype = sampler->dtype;
+    d.m = n_chains;
+    d.n = n_draws;
+    d.D = target->dim;
+    d.seed = seed;
+    d.noise_sd = target->noise_sd;
+    d.step_size = sampler->step_size;
+    d.max_depth = sampler->max_depth;
+    d.n_stages = sampler->n_stages;
+    for (int i = 0; i < 4; ++i) d.scales[i] = sampler->scales[i];
+    const size_t es = d.dtype == FSMMC_F32 ? 4 : 8;
+    const size_t m = (size_t)d.m;
+
+    d.EPL = ess_supported_epl(d.D, d.dtype);
+    d.Dp = 64 * d.EPL;
+    const size_t Dp = (size_t)d.Dp;
+
+    HIP_TRY_JOB(hipHostMalloc((void**)&job->h_ctr, 8 * sizeof(unsigned long long), hipHostMallocDefault));
+    ALLOC(d.ctr, 8 * sizeof(unsigned long long));
+    ALLOC(d.k, m * 4);
+    ALLOC(d.t, m * 4);
+    ALLOC(d.evals, m * 4);
+    ALLOC(d.budget, m * 8);
+    ALLOC(d.x, m * Dp * es);
+    ALLOC(d.lx, m * es);
+    ALLOC(d.theta, m * es);
+    ALLOC(d.tmin, m * es);
+    ALLOC(d.tmax, m * es);
+    ALLOC(d.logy, m * es);
+    ALLOC(d.sink, m * es);
+    ALLOC(d.maxN, (size_t)d.n * 4);
+    ALLOC(d.counts, m * (size_t)d.n * 4);
+    ALLOC(d.L, Dp * Dp * es);
+    ALLOC(d.y, Dp * es);
+
+    // ellipse window: about 1 GiB of directions, 4..256 draws, at most n
+    int W = tune && tune->window > 0 ? tune->window : 0;
+    if (!W) {
+        const double per_draw = (double)m * (double)Dp * (double)es;
+        W = 4;
+        while (W < 256 && 2.0 * W * per_draw <= 1073741824.0) W *= 2;
+    }
+    d.W = std::max(1, std::min(W, d.n));
+    ALLOC(d.nu, m * (size_t)d.W * Dp * es);
+
+    if (out_samples) {
+        d.out = out_samples;
+    } else {
+        ALLOC(d.out, m * (size_t)d.n * (size_t)d.D * es);
+    }
+
+    // target data
+    {
+        fsmmc_status s2 = stage_lower(job, target->chol_L, d.D, d.Dp, es, d.L);
+        if (s2 != FSMMC_OK) {
+            job_release(job);
+            return s2;
+        }
+    }
+    HIP_TRY_JOB(hipMemcpyAsync(d.y, target->y, (size_t)d.D * es, hipMemcpyDeviceToDevice, job->stream));
+
+    // k = S_1 (INIT), t = 0
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((d.m + 255) / 256), dim3(256), 0, job->stream, d.k, 1, d.m);
+    HIP_TRY_JOB(hipGetLastError());
+    if (x0)
+        HIP_TRY_JOB(hipMemcpy2DAsync(d.x, Dp * es, x0, (size_t)d.D * es, (size_t)d.D * es, m,
+                                     hipMemcpyDeviceToDevice, job->stream));
+    HIP_TRY_JOB(ess_prior_draw(d, x0, job->stream));
+    job->launches += x0 ? 2 : 3;
+    *out = job;
+    return FSMMC_OK;
+}
+
+static fsmmc_status read_ctr(fsmmc_job* job)
+{
+    HIP_TRY(hipMemcpyAsync(job->h_ctr, job->d.ctr, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           job->stream));
+    HIP_TRY(hipStreamSynchronize(job->stream));
+    harvest(job);
+    return FSMMC_OK;
+}
+
+static fsmmc_status progress(fsmmc_job* job, std::vector<uint32_t>& t, std::vector<int32_t>* k)
+{
+    t.resize(job->d.m);
+    HIP_TRY(hipMemcpyAsync(t.data(), job->d.t, t.size() * 4, hipMemcpyDeviceToHost, job->stream));
+    if (k) {
+        k->resize(job->d.m);
+        HIP_TRY(hipMemcpyAsync(k->data(), job->d.k, k->size() * 4, hipMemcpyDeviceToHost, job->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(job->stream));
+    return FSMMC_OK;
+}
+
+fsmmc_status fsmmc_step_fsm(fsmmc_job* job, int64_t max_steps, int32_t* all_done)
+{
+    if (!job) return fail(FSMMC_EINVAL, "job is NULL");
+    JobDev& d = job->d;
+    HIP_TRY(hipSetDevice(job->ctx->device));
+    const int64_t b = max_steps > 0 ? max_steps : INT64_MAX;
+    hipLaunchKernelGGL(fill_i64_kernel, dim3((d.m + 255) / 256), dim3(256), 0, job->stream, d.budget, b, d.m);
+    HIP_TRY(hipGetLastError());
+    job->launches++;
+    unsigned long long active = 1;
+    for (;;) {
+        HIP_TRY(hipMemsetAsync(d.ctr + 3, 0, 2 * sizeof(unsigned long long), job->stream));
+        HIP_TRY(launch(job, KC_G, [&] { return ess_fill_window(d, job->stream); }));
+        HIP_TRY(launch(job, KC_FSM, [&] { return ess_fsm_round(d, job->stream); }));
+        fsmmc_status s = read_ctr(job);
+        if (s != FSMMC_OK) return s;
+        active = job->h_ctr[4];
+        if (active == 0 || job->h_ctr[3] == 0) break;
+    }
+    if (all_done) *all_done = active == 0 ? 1 : 0;
+    return FSMMC_OK;
+}
+
+fsmmc_status fsmmc_step_synchronized(fsmmc_job* job, int32_t n_draws, int32_t mode, int32_t* all_done)
+{
+    if (!job) return fail(FSMMC_EINVAL, "job is NULL");
+    if (mode != FSMMC_SYNC_VMAP && mode != FSMMC_SYNC_COMPACT) return fail(FSMMC_EINVAL, "bad mode");
+    JobDev& d = job->d;
+    HIP_TRY(hipSetDevice(job->ctx->device));
+    std::vector<uint32_t> t;
+    std::vector<int32_t> k;
+    fsmmc_status s = progress(job, t, &k);
+    if (s != FSMMC_OK) return s;
+    const uint32_t t0 = t[0];
+    for (int i = 0; i < d.m; ++i)
+        if (t[i] != t0 || k[i] != 1)
+            return fail(FSMMC_EINVAL, "chains are not synchronized at a draw boundary");
+    const uint32_t t1 = std::min<uint32_t>((uint32_t)d.n, t0 + (uint32_t)std::max(n_draws, 0));
+    uint32_t wstart = t0;
+    for (uint32_t dr = t0; dr < t1; ++dr) {
+        if (dr == t0 || dr - wstart == (uint32_t)d.W) {
+            wstart = dr;
+            HIP_TRY(launch(job, KC_G, [&] { return ess_fill_window(d, job->stream); }));
+        }
+        const uint32_t slot = dr - wstart;
+        HIP_TRY(launch(job, KC_SYNC, [&] { return ess_sync_draw(d, dr, slot, job->stream); }));
+        if (mode == FSMMC_SYNC_VMAP)
+            HIP_TRY(launch(job, KC_PAD, [&] { return ess_pad_draw(d, dr, slot, job->stream); }));
+    }
+    HIP_TRY(hipStreamSynchronize(job->stream));
+    harvest(job);
+    if (all_done) *all_done = t1 >= (uint32_t)d.n ? 1 : 0;
+    return FSMMC_OK;
+}
+
+fsmmc_status fsmmc_collect_samples(fsmmc_job* job, int32_t b, int32_t e, void* dst, int32_t dst_is_host)
+{
+    if (!job || !dst) return fail(FSMMC_EINVAL, "job or dst is NULL");
+    JobDev& d = job->d;
+    if (b < 0 || e > d.n || b >= e) return fail(FSMMC_EINVAL, "bad draw range");
+    std::vector<uint32_t> t;
+    fsmmc_status s = progress(job, t, nullptr);
+    if (s != FSMMC_OK) return s;
+    for (uint32_t v : t)
+        if (v < (uint32_t)e) return fail(FSMMC_ENOTDONE, "draws not produced yet");
+    const size_t es = d.dtype == FSMMC_F32 ? 4 : 8;
+    const size_t row = (size_t)d.D * es;
+    HIP_TRY(hipMemcpy2DAsync(dst, (size_t)(e - b) * row, (const char*)d.out + (size_t)b * row, (size_t)d.n * row,
+                             (size_t)(e - b) * row, (size_t)d.m,
+                             dst_is_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, job->stream));
+    HIP_TRY(hipStreamSynchronize(job->stream));
+    return FSMMC_OK;
+}
+
+fsmmc_status fsmmc_collect_counts(fsmmc_job* job, int32_t* dst)
+{
+    if (!job || !dst) return fail(FSMMC_EINVAL, "job or dst is NULL");
+    HIP_TRY(hipMemcpyAsync(dst, job->d.counts, (size_t)job->d.m * job->d.n * 4, hipMemcpyDeviceToHost,
+                           job->stream));
+    HIP_TRY(hipStreamSynchronize(job->stream));
+    return FSMMC_OK;
+}
+
+fsmmc_status fsmmc_chain_progress(fsmmc_job* job, uint32_t* dst)
+{
+    if (!job || !dst) return fail(FSMMC_EINVAL, "job or dst is NULL");
+    std::vector<uint32_t> t;
+    fsmmc_status s = progress(job, t, nullptr);
+    if (s != FSMMC_OK) return s;
+    std::memcpy(dst, t.data(), t.size() * 4);
+    return FSMMC_OK;
+}
+
+fsmmc_status fsmmc_job_stats(fsmmc_job* job, fsmmc_stats* out)
+{
+    if (!job || !out) return fail(FSMMC_EINVAL, "job or out is NULL");
+    std::vector<uint32_t> t;
+    fsmmc_status s = progress(job, t, nullptr);
+    if (s != FSMMC_OK) return s;
+    s = read_ctr(job);
+    if (s != FSMMC_OK) return s;
+    std::memset(out, 0, sizeof(*out));
+    out->steps = (int64_t)job->h_ctr[0];
+    out->padded_steps = (int64_t)job->h_ctr[1];
+    out->guard_trips = (int32_t)job->h_ctr[2];
+    for (uint32_t v : t) {
+        out->draws += v;
+        out->chains_done += v >= (uint32_t)job->d.n;
+    }
+    out->launches = job->launches;
+    for (int c = 0; c < 4; ++c) {
+        out->kernel_ms[c] = job->kms[c];
+        out->kernel_launches[c] = job->klaunch[c];
+    }
+    return FSMMC_OK;
+}
+
+fsmmc_status fsmmc_job_sync(fsmmc_job* job)
+{
+    if (!job) return fail(FSMMC_EINVAL, "job is NULL");
+    HIP_TRY(hipStreamSynchronize(job->stream));
+    return FSMMC_OK;
+}
+
+fsmmc_status fsmmc_job_free(fsmmc_job* job)
+{
+    if (!job) return fail(FSMMC_EINVAL, "job is NULL");
+    job_release(job);
+    return FSMMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,186 @@
+// fsmmc_device.h -- device building blocks shared by every sampler kernel:
+// counter-based random streams, wave-level reductions, target terms.
+//
+// Everything here is deterministic and keyed only by (seed, chain, draw,
+// role, sub-step, block): nothing depends on the thread, wave, workgroup,
+// launch or schedule, so a chain's draws are the same whichever kernel
+// (FSM or synchronized) and whichever launch shape computes them.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fsmmc {
+
+// ---------------------------------------------------------------- RNG
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): multipliers
+// 0xD2511F53 / 0xCD9E8D57, Weyl key increments 0x9E3779B9 / 0xBB67AE85.
+struct Ctr4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ Ctr4 philox10(Ctr4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        Ctr4 n;
+        n.x = hi1 ^ c.y ^ k0;
+        n.y = lo1;
+        n.z = hi0 ^ c.w ^ k1;
+        n.w = lo0;
+        c = n;
+    }
+    return c;
+}
+
+enum Role : uint32_t {
+    ROLE_NU = 1,
+    ROLE_INIT = 2,
+    ROLE_THRESH = 3,
+    ROLE_ANGLE = 4,
+    ROLE_MOM = 5,
+    ROLE_DIR = 6,
+    ROLE_LEAF = 7,
+    ROLE_MERGE = 8,
+    ROLE_PROP = 9,
+    ROLE_ACC = 10
+};
+
+__device__ __forceinline__ Ctr4 stream_block(uint64_t seed, uint32_t chain, uint32_t draw, uint32_t role,
+                                             uint32_t sub, uint32_t block)
+{
+    Ctr4 c{chain, draw, (role << 24) | (sub & 0xFFFFFFu), block};
+    return philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// u = ((w >> 9) + 1/2) 2^-23: 24 significant bits, exact in both precisions,
+// strictly inside (0, 1).
+template <typename T>
+__device__ __forceinline__ T u01(uint32_t w);
+template <>
+__device__ __forceinline__ float u01<float>(uint32_t w)
+{
+    return ((float)(w >> 9) + 0.5f) * 0x1p-23f;
+}
+template <>
+__device__ __forceinline__ double u01<double>(uint32_t w)
+{
+    return ((double)(w >> 9) + 0.5) * 0x1p-23;
+}
+
+template <typename T>
+__device__ __forceinline__ T uniform(uint64_t seed, uint32_t chain, uint32_t draw, uint32_t role, uint32_t sub)
+{
+    return u01<T>(stream_block(seed, chain, draw, role, sub, 0).x);
+}
+
+// Box-Muller on one word pair: (r cos 2 pi u2, r sin 2 pi u2), r = sqrt(-2 ln u1).
+__device__ __forceinline__ void box_muller(uint32_t w1, uint32_t w2, float& z0, float& z1)
+{
+    const float u1 = u01<float>(w1), u2 = u01<float>(w2);
+    const float r = sqrtf(-2.0f * logf(u1));
+    float s, c;
+    sincospif(2.0f * u2, &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+__device__ __forceinline__ void box_muller(uint32_t w1, uint32_t w2, double& z0, double& z1)
+{
+    const double u1 = u01<double>(w1), u2 = u01<double>(w2);
+    const double r = sqrt(-2.0 * log(u1));
+    double s, c;
+    sincospi(2.0 * u2, &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
+// The four normals d = 4b .. 4b+3 of a (role, sub) vector stream.
+template <typename T>
+__device__ __forceinline__ void normals4(uint64_t seed, uint32_t chain, uint32_t draw, uint32_t role,
+                                         uint32_t sub, uint32_t b, T z[4])
+{
+    const Ctr4 w = stream_block(seed, chain, draw, role, sub, b);
+    box_muller(w.x, w.y, z[0], z[1]);
+    box_muller(w.z, w.w, z[2], z[3]);
+}
+
+// Normal d of a (role, sub) vector stream (computes its whole block).
+template <typename T>
+__device__ __forceinline__ T normal_at(uint64_t seed, uint32_t chain, uint32_t draw, uint32_t role,
+                                       uint32_t sub, uint32_t d)
+{
+    const Ctr4 w = stream_block(seed, chain, draw, role, sub, d >> 2);
+    T z0, z1;
+    if ((d & 2u) == 0)
+        box_muller(w.x, w.y, z0, z1);
+    else
+        box_muller(w.z, w.w, z0, z1);
+    return (d & 1u) ? z1 : z0;
+}
+
+// ---------------------------------------------------------------- waves
+// Butterfly sum over the 64 lanes of a wave: every lane ends with the same
+// bits (each step adds a commutative pair), in a fixed order.
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------- math
+template <typename T>
+struct M;
+template <>
+struct M<float> {
+    static __device__ __forceinline__ float exp_(float a) { return __expf(a); }
+    static __device__ __forceinline__ float log_(float a) { return __logf(a); }
+    static __device__ __forceinline__ float log1p_(float a) { return log1pf(a); }
+    static __device__ __forceinline__ float expm1_(float a) { return expm1f(a); }
+    static __device__ __forceinline__ void sincos_(float a, float* s, float* c) { sincosf(a, s, c); }
+    static __device__ __forceinline__ float fma_(float a, float b, float c) { return fmaf(a, b, c); }
+    // softplus(a) = max(a, 0) + log(1 + e^-|a|)
+    static __device__ __forceinline__ float softplus(float a)
+    {
+        return fmaxf(a, 0.0f) + __logf(1.0f + __expf(-fabsf(a)));
+    }
+};
+template <>
+struct M<double> {
+    static __device__ __forceinline__ double exp_(double a) { return exp(a); }
+    static __device__ __forceinline__ double log_(double a) { return log(a); }
+    static __device__ __forceinline__ double log1p_(double a) { return log1p(a); }
+    static __device__ __forceinline__ double expm1_(double a) { return expm1(a); }
+    static __device__ __forceinline__ void sincos_(double a, double* s, double* c) { sincos(a, s, c); }
+    static __device__ __forceinline__ double fma_(double a, double b, double c) { return fma(a, b, c); }
+    static __device__ __forceinline__ double softplus(double a)
+    {
+        return fmax(a, 0.0) + log1p(exp(-fabs(a)));
+    }
+};
+
+template <typename T>
+struct Pi;
+template <>
+struct Pi<float> {
+    static constexpr float two_pi = 6.28318530717958647692f;
+};
+template <>
+struct Pi<double> {
+    static constexpr double two_pi = 6.28318530717958647692;
+};
+
+}  // namespace fsmmc

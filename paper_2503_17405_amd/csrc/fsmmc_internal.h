@@ -1,0 +1,72 @@
+// fsmmc_internal.h -- host-side declarations shared by the C ABI and the
+// per-sampler launch code.  Not installed; not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fsmmc.h"
+
+namespace fsmmc {
+
+constexpr int kEssMaxEvals = 10000;  // evaluation guard of one ESS draw
+
+// Device state of one job.  Chain arrays are structure-of-arrays of length m;
+// vector state is m x Dp (one chain's vector contiguous, padded to Dp).
+struct JobDev {
+    // problem
+    int kind = 0;    // sampler kind
+    int target = 0;  // target kind
+    int dtype = 0;
+    int m = 0, n = 0, D = 0, Dp = 0, EPL = 0;
+    int N = 0, Np = 0;  // LOGREG rows (padded)
+    uint64_t seed = 0;
+    double noise_sd = 0;
+    double step_size = 0;
+    int max_depth = 0, n_stages = 0;
+    double scales[4] = {0, 0, 0, 0};
+
+    // target data (owned copies)
+    void* L = nullptr;  // Dp x Dp, zero padded (GP)
+    void* y = nullptr;  // Dp (GP) or Np (LOGREG) labels / observations
+    void* X = nullptr;  // LOGREG: Np x Dp, zero padded
+    void* prec = nullptr;
+
+    // common chain state
+    int32_t* k = nullptr;      // FSM state label
+    uint32_t* t = nullptr;     // draws done
+    int32_t* evals = nullptr;  // loop count of the draw in progress
+    int64_t* budget = nullptr; // steps left in the current call
+    void* x = nullptr;         // m x Dp current state
+    void* lx = nullptr;        // m: cached log-likelihood / log density / potential
+
+    // ESS
+    void* theta = nullptr;
+    void* tmin = nullptr;
+    void* tmax = nullptr;
+    void* logy = nullptr;
+    void* nu = nullptr;  // m x W x Dp ellipse directions of the current window
+    int W = 0;
+
+    // outputs
+    void* out = nullptr;  // m x n x D
+    int32_t* counts = nullptr;  // m x n
+
+    // counters (device): [0] steps, [1] padded steps, [2] guard trips,
+    // [3] chains still short of their window / budget, [4] active chains
+    unsigned long long* ctr = nullptr;
+    int32_t* maxN = nullptr;  // per draw (sync)
+    void* sink = nullptr;     // m, discarded results of padded bodies
+};
+
+// ESS launchers (ess.hip)
+hipError_t ess_prior_draw(const JobDev& j, const void* x0, hipStream_t s);
+hipError_t ess_fill_window(const JobDev& j, hipStream_t s);
+hipError_t ess_fsm_round(const JobDev& j, hipStream_t s);
+hipError_t ess_sync_draw(const JobDev& j, uint32_t draw, uint32_t slot, hipStream_t s);
+hipError_t ess_pad_draw(const JobDev& j, uint32_t draw, uint32_t slot, hipStream_t s);
+int ess_supported_epl(int D, int dtype);
+
+}  // namespace fsmmc

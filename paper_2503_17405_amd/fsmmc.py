@@ -1,0 +1,253 @@
+"""Thin ctypes binding of libfsmmc (include/fsmmc.h).
+
+Argument marshalling only: every step of the sampling path runs in the HIP
+library.  PyTorch supplies device memory (tensors' data pointers) and the
+stream.  Importing this module loads ``libfsmmc.so``; if it is missing the
+import raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfsmmc.so")
+
+OK, EINVAL, ENOMEM, EBUDGET, EDEVICE, EBUSY, ENOTDONE, ENOTSUP = range(8)
+GP_GAUSS, GP_LOGISTIC, LOGREG, FUNNEL, GAUSS_DIAG = range(5)
+ESS, NUTS, DRMH = range(3)
+F32, F64 = 0, 1
+SYNC_VMAP, SYNC_COMPACT = 0, 1
+
+# every symbol the header declares
+EXPORTS = [
+    "fsmmc_ctx_create", "fsmmc_ctx_destroy", "fsmmc_ctx_bytes_in_use", "fsmmc_init_chains",
+    "fsmmc_step_fsm", "fsmmc_step_synchronized", "fsmmc_collect_samples", "fsmmc_collect_counts",
+    "fsmmc_chain_progress", "fsmmc_job_stats", "fsmmc_job_sync", "fsmmc_job_free",
+    "fsmmc_last_error", "fsmmc_version",
+]
+
+
+class TargetSpec(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("n_data", C.c_int32),
+                ("reserved", C.c_int32), ("X", C.c_void_p), ("y", C.c_void_p),
+                ("chol_L", C.c_void_p), ("prec", C.c_void_p), ("noise_sd", C.c_double)]
+
+
+class SamplerSpec(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dtype", C.c_int32), ("max_depth", C.c_int32),
+                ("n_stages", C.c_int32), ("step_size", C.c_double), ("scales", C.c_double * 4)]
+
+
+class Tune(C.Structure):
+    _fields_ = [("window", C.c_int32), ("timing", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("padded_steps", C.c_int64), ("draws", C.c_int64),
+                ("chains_done", C.c_int32), ("guard_trips", C.c_int32), ("launches", C.c_int32),
+                ("reserved", C.c_int32), ("kernel_ms", C.c_double * 4),
+                ("kernel_launches", C.c_int32 * 4)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d["kernel_ms"] = list(self.kernel_ms)
+        d["kernel_launches"] = list(self.kernel_launches)
+        return d
+
+
+class FsmmcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("fsmmc error %d: %s" % (status, msg))
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libfsmmc.so is not built (run __graft_entry__.build() or "
+                          "python paper_2503_17405_amd/build.py)")
+    L = C.CDLL(LIB_PATH)
+    p, i32, i64, u64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_size_t
+    pp = C.POINTER(C.c_void_p)
+    sigs = {
+        "fsmmc_ctx_create": ([C.c_int, sz, pp], C.c_int),
+        "fsmmc_ctx_destroy": ([p], C.c_int),
+        "fsmmc_ctx_bytes_in_use": ([p], sz),
+        "fsmmc_init_chains": ([p, p, p, i32, i32, u64, p, p, p, p, pp], C.c_int),
+        "fsmmc_step_fsm": ([p, i64, p], C.c_int),
+        "fsmmc_step_synchronized": ([p, i32, i32, p], C.c_int),
+        "fsmmc_collect_samples": ([p, i32, i32, p, i32], C.c_int),
+        "fsmmc_collect_counts": ([p, p], C.c_int),
+        "fsmmc_chain_progress": ([p, p], C.c_int),
+        "fsmmc_job_stats": ([p, p], C.c_int),
+        "fsmmc_job_sync": ([p], C.c_int),
+        "fsmmc_job_free": ([p], C.c_int),
+        "fsmmc_last_error": ([], C.c_char_p),
+        "fsmmc_version": ([], C.c_char_p),
+    }
+    for name, (args, res) in sigs.items():
+        f = getattr(L, name)
+        f.argtypes, f.restype = args, res
+    return L
+
+
+lib = _load()
+
+
+def _check(status):
+    if status != OK:
+        raise FsmmcError(status, lib.fsmmc_last_error().decode())
+
+
+def version():
+    return lib.fsmmc_version().decode()
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------- C names
+def fsmmc_ctx_create(device=0, hbm_budget_bytes=0):
+    out = C.c_void_p()
+    _check(lib.fsmmc_ctx_create(device, hbm_budget_bytes, C.byref(out)))
+    return out
+
+
+def fsmmc_ctx_destroy(ctx):
+    _check(lib.fsmmc_ctx_destroy(ctx))
+
+
+def fsmmc_init_chains(ctx, target, sampler, n_chains, n_draws, seed, x0=None, out_samples=None,
+                      stream=None, tune=None):
+    out = C.c_void_p()
+    _check(lib.fsmmc_init_chains(ctx, C.byref(target), C.byref(sampler), n_chains, n_draws,
+                                 seed, _ptr(x0), _ptr(out_samples), _stream_ptr(stream),
+                                 None if tune is None else C.byref(tune), C.byref(out)))
+    return out
+
+
+def fsmmc_step_fsm(job, max_steps=0):
+    done = C.c_int32()
+    _check(lib.fsmmc_step_fsm(job, max_steps, C.byref(done)))
+    return bool(done.value)
+
+
+def fsmmc_step_synchronized(job, n_draws, mode=SYNC_VMAP):
+    done = C.c_int32()
+    _check(lib.fsmmc_step_synchronized(job, n_draws, mode, C.byref(done)))
+    return bool(done.value)
+
+
+def fsmmc_collect_samples(job, draw_begin, draw_end, dst, dst_is_host):
+    ptr = C.c_void_p(dst.ctypes.data) if dst_is_host else _ptr(dst)
+    _check(lib.fsmmc_collect_samples(job, draw_begin, draw_end, ptr, 1 if dst_is_host else 0))
+
+
+def fsmmc_collect_counts(job, dst):
+    _check(lib.fsmmc_collect_counts(job, C.c_void_p(dst.ctypes.data)))
+
+
+def fsmmc_chain_progress(job, dst):
+    _check(lib.fsmmc_chain_progress(job, C.c_void_p(dst.ctypes.data)))
+
+
+def fsmmc_job_stats(job):
+    s = Stats()
+    _check(lib.fsmmc_job_stats(job, C.byref(s)))
+    return s.as_dict()
+
+
+def fsmmc_job_sync(job):
+    _check(lib.fsmmc_job_sync(job))
+
+
+def fsmmc_job_free(job):
+    _check(lib.fsmmc_job_free(job))
+
+
+# ------------------------------------------------------------- convenience
+class Context:
+    def __init__(self, device=0, hbm_budget_bytes=0):
+        self.handle = fsmmc_ctx_create(device, hbm_budget_bytes)
+        self.device = device
+
+    def bytes_in_use(self):
+        return lib.fsmmc_ctx_bytes_in_use(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            fsmmc_ctx_destroy(self.handle)
+            self.handle = None
+
+
+def gp_target(chol_L, y, noise_sd=None):
+    """Target spec of a latent GP (tensors on the device, in the job dtype)."""
+    kind = GP_LOGISTIC if noise_sd is None else GP_GAUSS
+    spec = TargetSpec(kind, int(y.numel()), 0, 0, None, _ptr(y), _ptr(chol_L), None,
+                      float(noise_sd or 0.0))
+    return spec, (chol_L, y)
+
+
+def ess_sampler(dtype=F32):
+    return SamplerSpec(ESS, dtype, 0, 0, 0.0, (C.c_double * 4)())
+
+
+class Job:
+    """One sampling job: n_chains chains x n_draws draws of one target."""
+
+    def __init__(self, ctx, target, sampler, n_chains, n_draws, seed, x0=None, out=None,
+                 stream=None, window=0, timing=False):
+        import torch
+        spec, self._keep = target
+        self.sampler = sampler
+        self.m, self.n, self.dim = n_chains, n_draws, spec.dim
+        self.dtype = torch.float32 if sampler.dtype == F32 else torch.float64
+        tune = Tune(window, 1 if timing else 0) if (window or timing) else None
+        torch.cuda.synchronize()
+        self.handle = fsmmc_init_chains(ctx.handle, spec, sampler, n_chains, n_draws, seed, x0, out,
+                                        stream, tune)
+        self.out = out
+
+    def step_fsm(self, max_steps=0):
+        return fsmmc_step_fsm(self.handle, max_steps)
+
+    def step_synchronized(self, n_draws, mode=SYNC_VMAP):
+        return fsmmc_step_synchronized(self.handle, n_draws, mode)
+
+    def samples(self, b=0, e=None):
+        e = self.n if e is None else e
+        dst = np.zeros((self.m, e - b, self.dim),
+                       dtype=np.float32 if self.sampler.dtype == F32 else np.float64)
+        fsmmc_collect_samples(self.handle, b, e, dst, True)
+        return dst
+
+    def counts(self):
+        dst = np.zeros((self.m, self.n), dtype=np.int32)
+        fsmmc_collect_counts(self.handle, dst)
+        return dst
+
+    def progress(self):
+        dst = np.zeros(self.m, dtype=np.uint32)
+        fsmmc_chain_progress(self.handle, dst)
+        return dst
+
+    def stats(self):
+        return fsmmc_job_stats(self.handle)
+
+    def sync(self):
+        fsmmc_job_sync(self.handle)
+
+    def free(self):
+        if self.handle is not None:
+            fsmmc_job_free(self.handle)
+            self.handle = None

@@ -1,0 +1,67 @@
+"""Helpers of the GPU-vs-oracle parity tests (test code; calls the oracle).
+
+Per-draw error: ||x_gpu - x_orc||_2 / max(||x_orc||_2, 1).  A chain "flips"
+at the first draw whose loop count differs from the oracle's (a different
+number of shrinks, stages or leapfrogs); draws from the flip on are not
+compared.  A flip is a near-tie when the oracle's decision margin at the
+evaluation where the two runs part is below 64 eps32 (1 + sum |terms|).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import oracle as O
+
+EPS32 = np.finfo(np.float32).eps
+
+
+def compare_draws(gpu, orc, gpu_counts, orc_counts, first=100):
+    """Returns (max error before flips, flip draw per chain or -1)."""
+    m = gpu.shape[0]
+    n = min(first, gpu.shape[1])
+    flips = np.full(m, -1)
+    worst = 0.0
+    for j in range(m):
+        diff = np.nonzero(gpu_counts[j, :n] != orc_counts[j, :n])[0]
+        upto = n if diff.size == 0 else diff[0]
+        if diff.size:
+            flips[j] = diff[0]
+        if upto == 0:
+            continue
+        a = gpu[j, :upto].astype(np.float64)
+        b = orc[j, :upto]
+        err = np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1.0)
+        worst = max(worst, float(err.max()))
+    return worst, flips
+
+
+def ess_flip_margin(target, L, seed, chain, draw, x_prev, gpu_count, orc_count, noise_sd=None):
+    """Decision margin of the oracle at the evaluation where a GPU ESS chain
+    with a different loop count parted from it, and the magnitude scale."""
+    D = L.shape[0]
+    lx = O.gp_loglik(target, x_prev)
+    nu = L @ O.normals(seed, chain, draw, O.ROLE_NU, 0, D)
+    logy = lx + np.log(O.uniform(seed, chain, draw, O.ROLE_THRESH, 0))
+    theta = 2 * np.pi * O.uniform(seed, chain, draw, O.ROLE_ANGLE, 0)
+    tmin, tmax = theta - 2 * np.pi, theta
+    k_at = min(gpu_count, orc_count)  # the evaluation where the decisions differ
+    for ev in range(1, k_at + 1):
+        xp = x_prev * np.cos(theta) + nu * np.sin(theta)
+        lp = O.gp_loglik(target, xp)
+        if ev == k_at:
+            y = target.y
+            if noise_sd is None:
+                terms = np.sum(np.abs(y * xp)) + np.sum(np.logaddexp(0, xp))
+            else:
+                terms = np.sum((y - xp) ** 2) / (2 * noise_sd ** 2)
+            return abs(lp - logy), terms + abs(logy)
+        if theta < 0:
+            tmin = theta
+        else:
+            tmax = theta
+        theta = tmin + (tmax - tmin) * O.uniform(seed, chain, draw, O.ROLE_ANGLE, ev)
+    return np.inf, 0.0
+
+
+def is_near_tie(margin, terms, eps=EPS32):
+    return margin < 64 * eps * (1.0 + terms)

@@ -1,0 +1,190 @@
+"""GPU parity of elliptical slice sampling through the C ABI.
+
+* FSM runtime == synchronized runtime, bit for bit, per chain (the FSM
+  changes the schedule, not the draws: Sec. 1, Sec. 3.2).
+* GPU vs the FP64 oracle per draw: 1e-4 relative in FP32 over the first
+  100 draws (1e-10 in FP64) up to the first flip; every flip a near-tie.
+* Schedule independence: window sizes, step budgets and chunking give the
+  same bits.
+"""
+import numpy as np
+import pytest
+import torch
+
+import parity
+from oracle import diagnostics as Dg
+from oracle import oracle as O
+from paper_2503_17405_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2503_17405_amd import fsmmc
+    return fsmmc
+
+
+@pytest.fixture(scope="module")
+def ctx(F):
+    c = F.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a, dtype):
+    return torch.tensor(np.asarray(a), dtype=dtype, device="cuda")
+
+
+def gpu_ess(F, ctx, w, m, n, seed, fp64=False, noise_sd=None, runtime="fsm", window=0,
+            max_steps=0, x0=None):
+    dt = torch.float64 if fp64 else torch.float32
+    L, y = _dev(w["L"], dt), _dev(w["y"], dt)
+    x0t = None if x0 is None else _dev(x0, dt)
+    job = F.Job(ctx, F.gp_target(L, y, noise_sd), F.ess_sampler(F.F64 if fp64 else F.F32), m, n,
+                seed, x0=x0t, window=window)
+    try:
+        if runtime == "fsm":
+            for _ in range(100000):
+                if job.step_fsm(max_steps):
+                    break
+        else:
+            mode = F.SYNC_VMAP if runtime == "vmap" else F.SYNC_COMPACT
+            assert job.step_synchronized(n, mode)
+        return job.samples(), job.counts(), job.stats()
+    finally:
+        job.free()
+
+
+def oracle_ess(w, m, n, seed, noise_sd=None, x0=None):
+    tg = O.gp_target(w["y"], noise_sd=noise_sd)
+    draws, counts, guards = O.run_chains(tg, O.ess_sampler(w["L"]), seed, range(m), n, x0=x0)
+    assert guards == 0
+    return draws, counts, tg
+
+
+def test_ess_fp64_d16_oracle_parity(F, ctx):
+    w = inputs.gp_gauss(dim=16, lengthscale=0.2, jitter=1e-6, noise_sd=0.1, seed=1001)
+    S, C, st = gpu_ess(F, ctx, w, 64, 100, 1002, fp64=True, noise_sd=0.1)
+    R, RC, _ = oracle_ess(w, 64, 100, 1002, noise_sd=0.1)
+    err, flips = parity.compare_draws(S, R, C, RC, first=100)
+    print("fp64 d16: max rel err %.3g, flips %d" % (err, (flips >= 0).sum()))
+    assert (flips >= 0).sum() == 0
+    assert err <= 1e-10
+    assert st["guard_trips"] == 0 and st["chains_done"] == 64
+
+
+def test_ess_fp64_d16_closed_form(F, ctx):
+    # the GPU chains of the pinned oracle run reproduce the closed-form posterior
+    w = inputs.gp_gauss(dim=16, lengthscale=0.2, jitter=1e-6, noise_sd=0.1, seed=1001)
+    S, C, _ = gpu_ess(F, ctx, w, 64, 4000, 1002, fp64=True, noise_sd=0.1)
+    K, y = w["K"], w["y"]
+    A = np.linalg.solve(K + 0.01 * np.eye(16), np.eye(16))
+    mu, Sig = K @ A @ y, K - K @ A @ K
+    b = S[:, 400:, :]
+    for d in range(16):
+        assert abs(b[:, :, d].mean() - mu[d]) < 3 * Dg.mcse_mean(b[:, :, d])
+        assert abs(b[:, :, d].var() - Sig[d, d]) < 3 * Dg.mcse_var(b[:, :, d])
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_ess_fsm_equals_synchronized(F, ctx, fp64):
+    if fp64:
+        w = inputs.gp_gauss(dim=16, seed=1001)
+        kw = dict(noise_sd=0.1, fp64=True)
+    else:
+        w = inputs.gp_logistic(dim=300, lengthscale=0.05, jitter=1e-5, seed=77)
+        kw = {}
+    m, n = 258, 150
+    ref = gpu_ess(F, ctx, w, m, n, 5, runtime="vmap", **kw)
+    for runtime, window, steps in [("fsm", 0, 0), ("fsm", 1, 0), ("fsm", 7, 5), ("fsm", 64, 13),
+                                   ("compact", 0, 0)]:
+        S, C, st = gpu_ess(F, ctx, w, m, n, 5, runtime=runtime, window=window, max_steps=steps, **kw)
+        assert np.array_equal(S, ref[0]), (runtime, window, steps)
+        assert np.array_equal(C, ref[1]), (runtime, window, steps)
+        assert st["steps"] == C.sum()
+    # the vmap baseline ran max_j N_ij bodies for every chain and draw
+    C = ref[1]
+    assert ref[2]["steps"] + ref[2]["padded_steps"] == m * C.max(axis=0).sum()
+
+
+def test_ess_fp32_d1024_oracle_parity(F, ctx):
+    w = inputs.gp_logistic(dim=1024, lengthscale=0.05, jitter=1e-5, seed=2001)
+    m, n, seed = 64, 100, 2002
+    S, C, st = gpu_ess(F, ctx, w, m, n, seed)
+    R, RC, tg = oracle_ess(w, m, n, seed)
+    err, flips = parity.compare_draws(S, R, C, RC, first=100)
+    nflip = int((flips >= 0).sum())
+    bad = 0
+    for j in np.nonzero(flips >= 0)[0]:
+        t = flips[j]
+        x_prev = R[j, t - 1] if t > 0 else O.ess_init(w["L"], seed, int(j))
+        margin, terms = parity.ess_flip_margin(tg, w["L"], seed, int(j), int(t), x_prev,
+                                               int(C[j, t]), int(RC[j, t]))
+        bad += not parity.is_near_tie(margin, terms)
+    print("fp32 d1024: max rel err %.3g over pre-flip draws; chains with a flip %d/%d, "
+          "not near-tie %d" % (err, nflip, m, bad))
+    assert err <= 1e-4
+    assert bad == 0
+    assert nflip <= m // 4
+
+
+@pytest.mark.parametrize("D", [1, 17, 100, 333, 700])
+def test_ess_ragged_dims_oracle_parity(F, ctx, D):
+    w = inputs.gp_logistic(dim=D, lengthscale=0.1, jitter=1e-5, seed=D)
+    m, n = 37, 40
+    S, C, _ = gpu_ess(F, ctx, w, m, n, 9)
+    R, RC, _ = oracle_ess(w, m, n, 9)
+    err, flips = parity.compare_draws(S, R, C, RC, first=n)
+    assert err <= 1e-4, D
+    assert (flips >= 0).sum() <= 2
+
+
+def test_ess_explicit_x0(F, ctx):
+    w = inputs.gp_logistic(dim=64, lengthscale=0.1, seed=3)
+    x0 = np.random.default_rng(0).standard_normal((12, 64)) * 0.5
+    S, C, _ = gpu_ess(F, ctx, w, 12, 30, 4, x0=x0)
+    R, RC, _ = oracle_ess(w, 12, 30, 4, x0=x0)
+    err, flips = parity.compare_draws(S, R, C, RC, first=30)
+    assert err <= 1e-4 and (flips >= 0).sum() == 0
+
+
+def test_ess_step_budget_semantics(F, ctx):
+    w = inputs.gp_logistic(dim=128, lengthscale=0.1, seed=5)
+    L, y = _dev(w["L"], torch.float32), _dev(w["y"], torch.float32)
+    job = F.Job(ctx, F.gp_target(L, y), F.ess_sampler(F.F32), 40, 500, 11)
+    try:
+        assert not job.step_fsm(3)
+        assert job.stats()["steps"] == 3 * 40
+        assert not job.step_fsm(4)
+        assert job.stats()["steps"] == 7 * 40
+        prog = job.progress()
+        assert prog.max() <= 7
+        with pytest.raises(F.FsmmcError):
+            job.samples(0, 400)  # not produced yet
+        while not job.step_fsm(0):
+            pass
+        assert job.stats()["chains_done"] == 40
+    finally:
+        job.free()
+
+
+def test_ess_argument_errors(F, ctx):
+    w = inputs.gp_logistic(dim=8, seed=1)
+    L, y = _dev(w["L"], torch.float32), _dev(w["y"], torch.float32)
+    tgt = F.gp_target(L, y)
+    with pytest.raises(F.FsmmcError) as e:
+        F.Job(ctx, tgt, F.ess_sampler(F.F32), 0, 10, 1)
+    assert e.value.status == F.EINVAL
+    big = torch.zeros((2000, 2000), device="cuda")
+    with pytest.raises(F.FsmmcError) as e:
+        F.Job(ctx, F.gp_target(big, torch.zeros(2000, device="cuda")), F.ess_sampler(F.F32), 4, 4, 1)
+    assert e.value.status == F.ENOTSUP
+    small = F.Context(0, hbm_budget_bytes=1 << 20)
+    try:
+        with pytest.raises(F.FsmmcError) as e:
+            F.Job(small, tgt, F.ess_sampler(F.F32), 4096, 1000, 1)
+        assert e.value.status == F.EBUDGET
+        assert small.bytes_in_use() == 0
+    finally:
+        small.close()
