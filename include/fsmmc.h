@@ -192,6 +192,16 @@ fsmmc_status fsmmc_collect_samples(fsmmc_job* job, int32_t draw_begin, int32_t d
  * (Sec. 2.2, "Formalizing the problem").  Synchronises the job's stream. */
 fsmmc_status fsmmc_collect_counts(fsmmc_job* job, int32_t* dst);
 
+/* Evaluate the job's target at n_points positions with the same kernels the
+ * sampler uses (NUTS jobs: the potential U = -log pi and its gradient).
+ *   theta: device, n_points x dim positions (n_points <= n_chains);
+ *   grad:  device, n_points x dim output, or NULL;
+ *   U:     device, n_points output.
+ * Uses the job's scratch buffers: call it only between stepping calls.
+ * Synchronises the job's stream.  Errors: EINVAL, ENOTSUP (ESS jobs). */
+fsmmc_status fsmmc_eval_potential(fsmmc_job* job, int32_t n_points, const void* theta, void* grad,
+                                  void* U);
+
 /* Per-chain draw counters t_j (host dst, n_chains uint32).  Synchronises. */
 fsmmc_status fsmmc_chain_progress(fsmmc_job* job, uint32_t* dst);
 

@@ -573,6 +573,33 @@ double orc_leapfrog(const orc_target* t, double veps, double* th, double* p, dou
     return U;
 }
 
+/* Optional record of every branch decision of a NUTS draw: the distance of
+ * the compared quantity from its threshold and the magnitude of the terms
+ * it was computed from (used by the tests to classify near-ties). */
+typedef struct {
+    double* margin;
+    double* scale;
+    int32_t cap, n;
+} orc_trace;
+
+static __thread orc_trace* g_trace = NULL;
+
+static void trace(double margin, double scale)
+{
+    if (g_trace && g_trace->n < g_trace->cap) {
+        g_trace->margin[g_trace->n] = fabs(margin);
+        g_trace->scale[g_trace->n] = fabs(scale);
+        g_trace->n++;
+    }
+}
+
+static double abs_dot(const double* a, const double* b, int D)
+{
+    double s = 0.0;
+    for (int i = 0; i < D; ++i) s += fabs(a[i] * b[i]);
+    return s;
+}
+
 /* Store checkpoints for spans starting at leaf n, then test every aligned
  * span of size 2^k (k >= 1) ending at leaf n.  rhoS already includes p_n.
  * Returns 1 when some span is turning.                                   */
@@ -589,6 +616,10 @@ static int nuts_leaf_uturn(int D, int j, uint32_t n, const double* p, const doub
     for (int k = 1; k <= j; ++k) {
         if (((n + 1u) & ((1u << k) - 1u)) == 0u) {
             for (int i = 0; i < D; ++i) tmp[i] = rhoS[i] - ckr[(size_t)k * D + i];
+            if (g_trace) {
+                trace(dot(ckp + (size_t)k * D, tmp, D), abs_dot(ckp + (size_t)k * D, tmp, D));
+                trace(dot(p, tmp, D), abs_dot(p, tmp, D));
+            }
             if (dot(ckp + (size_t)k * D, tmp, D) <= 0.0 || dot(p, tmp, D) <= 0.0) turn = 1;
         }
     }
@@ -660,12 +691,17 @@ int orc_nuts_sample(const orc_target* t, double eps, int max_depth, uint64_t see
             double Un = orc_leapfrog(t, v * eps, the, pe, ge, w.ph);
             ++nleap;
             double wn = H0 - (Un + 0.5 * dot(pe, pe, D));
+            const double escale = fabs(H0) + fabs(Un) + 0.5 * dot(pe, pe, D);
+            trace(-wn - ORC_NUTS_DMAX, escale);
             if (!(-wn <= ORC_NUTS_DMAX)) {
                 invalid = 1;
                 diverged = 1;
                 break;
             }
             double Wn = logaddexp(Ws, wn);
+            if (n > 0)
+                trace(log(orc_uniform(seed, chain, draw, ORC_ROLE_LEAF, ((uint32_t)j << 16) | n)) - (wn - Wn),
+                      escale);
             if (log(orc_uniform(seed, chain, draw, ORC_ROLE_LEAF, ((uint32_t)j << 16) | n)) < wn - Wn) {
                 memcpy(w.thS, the, sizeof(double) * D);
                 memcpy(w.gS, ge, sizeof(double) * D);
@@ -684,6 +720,7 @@ int orc_nuts_sample(const orc_target* t, double eps, int max_depth, uint64_t see
         if (invalid) {
             stop = 1;
         } else {
+            trace(log(orc_uniform(seed, chain, draw, ORC_ROLE_MERGE, (uint32_t)j)) - (Ws - W), fabs(H0) + 1.0);
             if (log(orc_uniform(seed, chain, draw, ORC_ROLE_MERGE, (uint32_t)j)) < Ws - W) {
                 memcpy(w.thP, w.thS, sizeof(double) * D);
                 memcpy(w.gP, w.gS, sizeof(double) * D);
@@ -691,6 +728,10 @@ int orc_nuts_sample(const orc_target* t, double eps, int max_depth, uint64_t see
             }
             W = logaddexp(W, Ws);
             for (int i = 0; i < D; ++i) w.rho[i] += w.rhoS[i];
+            if (g_trace) {
+                trace(dot(w.pL, w.rho, D), abs_dot(w.pL, w.rho, D));
+                trace(dot(w.pR, w.rho, D), abs_dot(w.pR, w.rho, D));
+            }
             if (dot(w.pL, w.rho, D) <= 0.0 || dot(w.pR, w.rho, D) <= 0.0) {
                 stop = 1;
                 turned = 1;
@@ -991,4 +1032,20 @@ int orc_run_chain(const orc_target* t, const orc_sampler* sp, uint64_t seed, uin
     }
     if (steps) *steps = nsteps;
     return guards;
+}
+
+/* orc_nuts_sample with every branch decision recorded into (margin, scale)
+ * arrays of capacity cap; returns the number of leapfrogs, *n_dec the number
+ * of decisions recorded. */
+int orc_nuts_sample_traced(const orc_target* t, double eps, int max_depth, uint64_t seed,
+                           uint32_t chain, uint32_t draw, double* th, double* U, double* g,
+                           double* wsbuf, orc_nuts_info* info, double* margin, double* scale,
+                           int32_t cap, int32_t* n_dec)
+{
+    orc_trace tr = {margin, scale, cap, 0};
+    g_trace = &tr;
+    int r = orc_nuts_sample(t, eps, max_depth, seed, chain, draw, th, U, g, wsbuf, info);
+    g_trace = NULL;
+    *n_dec = tr.n;
+    return r;
 }

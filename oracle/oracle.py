@@ -96,6 +96,8 @@ def lib():
             L.orc_nuts_subtree_first_turn.argtypes = [i32, i32, p]
             L.orc_nuts_sample.restype = i32
             L.orc_nuts_sample.argtypes = [p, d, i32, u64, u32, u32, p, p, p, p, p]
+            L.orc_nuts_sample_traced.restype = i32
+            L.orc_nuts_sample_traced.argtypes = [p, d, i32, u64, u32, u32, p, p, p, p, p, p, p, i32, p]
             L.orc_ess_sample.restype = i32
             L.orc_ess_sample.argtypes = [p, p, u64, u32, u32, p, p, p]
             L.orc_dr_sample.restype = i32
@@ -260,6 +262,22 @@ def nuts_sample(target, eps, max_depth, seed, chain, draw, th, U, g):
                           C.byref(Uc), _ptr(g), _ptr(ws), C.byref(info))
     return th, Uc.value, g, dict(n_leapfrog=info.n_leapfrog, depth=info.depth,
                                   diverged=info.diverged, turned=info.turned)
+
+
+def nuts_decisions(target, eps, max_depth, seed, chain, draw, th, cap=1 << 16):
+    """Branch decisions of one NUTS draw from state th: arrays (margin, scale)."""
+    D = target.dim
+    th = _f64(th).copy()
+    U, g = potential(target, th, grad=True)
+    Uc = C.c_double(U)
+    ws = np.zeros(D * (13 + 2 * 16))
+    info = _NutsInfo()
+    mar, sca = np.zeros(cap), np.zeros(cap)
+    nd = C.c_int32()
+    lib().orc_nuts_sample_traced(target.ref, float(eps), int(max_depth), seed, chain, draw, _ptr(th),
+                                 C.byref(Uc), _ptr(g), _ptr(ws), C.byref(info), _ptr(mar), _ptr(sca),
+                                 cap, C.byref(nd))
+    return mar[:nd.value], sca[:nd.value]
 
 
 def ess_init(chol_L, seed, chain):

@@ -67,8 +67,9 @@ struct fsmmc_job {
     JobDev d;
     std::vector<void*> allocs;
     size_t bytes = 0;
-    unsigned long long* h_ctr = nullptr;  // pinned mirror of d.ctr
+    unsigned long long* h_ctr = nullptr;  // pinned: [0..7] mirror of d.ctr, [8..15] scratch reads
     int launches = 0;
+    uint32_t step = 0;  // NUTS runtime step counter (keys the per-step counters)
     // optional per-launch device timing
     bool timing = false;
     std::vector<hipEvent_t> pool;
@@ -247,8 +248,18 @@ static fsmmc_status validate(const fsmmc_target_spec* t, const fsmmc_sampler_spe
             return fail(FSMMC_ENOTSUP, "dim too large for this dtype");
         return FSMMC_OK;
     }
-    if (s->kind == FSMMC_NUTS || s->kind == FSMMC_DRMH)
-        return fail(FSMMC_ENOTSUP, "sampler not built into this library version");
+    if (s->kind == FSMMC_NUTS) {
+        if (t->kind != FSMMC_LOGREG) return fail(FSMMC_ENOTSUP, "NUTS is built for LOGREG targets");
+        if (s->dtype != FSMMC_F32) return fail(FSMMC_ENOTSUP, "NUTS is built for FP32");
+        if (!t->X || !t->y) return fail(FSMMC_EINVAL, "LOGREG target needs X and y");
+        if (t->n_data < 1) return fail(FSMMC_EINVAL, "n_data must be >= 1");
+        if (t->dim > 128) return fail(FSMMC_ENOTSUP, "NUTS dim must be <= 128");
+        if (s->max_depth < 1 || s->max_depth > 15) return fail(FSMMC_EINVAL, "max_depth must be in [1, 15]");
+        if (!(s->step_size > 0.0) || !std::isfinite(s->step_size))
+            return fail(FSMMC_EINVAL, "step_size must be > 0");
+        return FSMMC_OK;
+    }
+    if (s->kind == FSMMC_DRMH) return fail(FSMMC_ENOTSUP, "sampler not built into this library version");
     return fail(FSMMC_EINVAL, "unknown sampler kind");
 }
 
@@ -297,62 +308,95 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
     const size_t es = d.dtype == FSMMC_F32 ? 4 : 8;
     const size_t m = (size_t)d.m;
 
-    d.EPL = ess_supported_epl(d.D, d.dtype);
-    d.Dp = 64 * d.EPL;
-    const size_t Dp = (size_t)d.Dp;
-
-    HIP_TRY_JOB(hipHostMalloc((void**)&job->h_ctr, 8 * sizeof(unsigned long long), hipHostMallocDefault));
+    HIP_TRY_JOB(hipHostMalloc((void**)&job->h_ctr, 16 * sizeof(unsigned long long), hipHostMallocDefault));
     ALLOC(d.ctr, 8 * sizeof(unsigned long long));
     ALLOC(d.k, m * 4);
     ALLOC(d.t, m * 4);
     ALLOC(d.evals, m * 4);
     ALLOC(d.budget, m * 8);
-    ALLOC(d.x, m * Dp * es);
     ALLOC(d.lx, m * es);
-    ALLOC(d.theta, m * es);
-    ALLOC(d.tmin, m * es);
-    ALLOC(d.tmax, m * es);
-    ALLOC(d.logy, m * es);
-    ALLOC(d.sink, m * es);
-    ALLOC(d.maxN, (size_t)d.n * 4);
     ALLOC(d.counts, m * (size_t)d.n * 4);
-    ALLOC(d.L, Dp * Dp * es);
-    ALLOC(d.y, Dp * es);
-
-    // ellipse window: about 1 GiB of directions, 4..256 draws, at most n
-    int W = tune && tune->window > 0 ? tune->window : 0;
-    if (!W) {
-        const double per_draw = (double)m * (double)Dp * (double)es;
-        W = 4;
-        while (W < 256 && 2.0 * W * per_draw <= 1073741824.0) W *= 2;
-    }
-    d.W = std::max(1, std::min(W, d.n));
-    ALLOC(d.nu, m * (size_t)d.W * Dp * es);
-
     if (out_samples) {
         d.out = out_samples;
     } else {
         ALLOC(d.out, m * (size_t)d.n * (size_t)d.D * es);
     }
+    d.tstop = (uint32_t)d.n;
 
-    // target data
-    {
+    if (d.kind == FSMMC_ESS) {
+        d.EPL = ess_supported_epl(d.D, d.dtype);
+        d.Dp = 64 * d.EPL;
+        const size_t Dp = (size_t)d.Dp;
+        ALLOC(d.x, m * Dp * es);
+        ALLOC(d.theta, m * es);
+        ALLOC(d.tmin, m * es);
+        ALLOC(d.tmax, m * es);
+        ALLOC(d.logy, m * es);
+        ALLOC(d.sink, m * es);
+        ALLOC(d.maxN, (size_t)d.n * 4);
+        ALLOC(d.L, Dp * Dp * es);
+        ALLOC(d.y, Dp * es);
+        // ellipse window: about 1 GiB of directions, 4..256 draws, at most n
+        int W = tune && tune->window > 0 ? tune->window : 0;
+        if (!W) {
+            const double per_draw = (double)m * (double)Dp * (double)es;
+            W = 4;
+            while (W < 256 && 2.0 * W * per_draw <= 1073741824.0) W *= 2;
+        }
+        d.W = std::max(1, std::min(W, d.n));
+        while ((int64_t)d.W * d.m > (int64_t)1 << 30 && d.W > 1) d.W /= 2;
+        ALLOC(d.nu, m * (size_t)d.W * Dp * es);
         fsmmc_status s2 = stage_lower(job, target->chol_L, d.D, d.Dp, es, d.L);
         if (s2 != FSMMC_OK) {
             job_release(job);
             return s2;
         }
-    }
-    HIP_TRY_JOB(hipMemcpyAsync(d.y, target->y, (size_t)d.D * es, hipMemcpyDeviceToDevice, job->stream));
-
-    // k = S_1 (INIT), t = 0
-    hipLaunchKernelGGL(fill_i32_kernel, dim3((d.m + 255) / 256), dim3(256), 0, job->stream, d.k, 1, d.m);
-    HIP_TRY_JOB(hipGetLastError());
-    if (x0)
-        HIP_TRY_JOB(hipMemcpy2DAsync(d.x, Dp * es, x0, (size_t)d.D * es, (size_t)d.D * es, m,
+        HIP_TRY_JOB(hipMemcpyAsync(d.y, target->y, (size_t)d.D * es, hipMemcpyDeviceToDevice, job->stream));
+        // k = S_1 (INIT), t = 0
+        hipLaunchKernelGGL(fill_i32_kernel, dim3((d.m + 255) / 256), dim3(256), 0, job->stream, d.k, 1, d.m);
+        HIP_TRY_JOB(hipGetLastError());
+        if (x0)
+            HIP_TRY_JOB(hipMemcpy2DAsync(d.x, Dp * es, x0, (size_t)d.D * es, (size_t)d.D * es, m,
+                                         hipMemcpyDeviceToDevice, job->stream));
+        HIP_TRY_JOB(ess_prior_draw(d, x0, job->stream));
+        job->launches += x0 ? 2 : 3;
+    } else {  // NUTS on logistic regression
+        d.EPL = d.D <= 64 ? 1 : 2;
+        d.Dp = 64 * d.EPL;
+        const size_t Dp = (size_t)d.Dp;
+        d.N = target->n_data;
+        d.slice_rows = 512;
+        d.nslices = (d.N + d.slice_rows - 1) / d.slice_rows;
+        d.Np = d.nslices * d.slice_rows;
+        d.nvec = nuts_nvec(d.max_depth);
+        ALLOC(d.jd, m * 4);
+        ALLOC(d.vdir, m * 4);
+        ALLOC(d.nn, m * 4);
+        ALLOC(d.flags, m * 4);
+        ALLOC(d.H0, m * 4);
+        ALLOC(d.Wsum, m * 4);
+        ALLOC(d.Wsub, m * 4);
+        ALLOC(d.US, m * 4);
+        ALLOC(d.V, m * (size_t)d.nvec * Dp * 4);
+        ALLOC(d.Thq, m * Dp * 4);
+        ALLOC(d.Gres, m * Dp * 4);
+        ALLOC(d.Ures, m * 4);
+        ALLOC(d.req, m * 4);
+        ALLOC(d.list, m * 4);
+        ALLOC(d.count, 64);
+        ALLOC(d.Gpart, (size_t)d.nslices * m * Dp * 4);
+        ALLOC(d.Upart, (size_t)d.nslices * m * 4);
+        ALLOC(d.wctr, 64);
+        ALLOC(d.X, (size_t)d.Np * Dp * 4);
+        ALLOC(d.y, (size_t)d.Np * 4);
+        HIP_TRY_JOB(hipMemcpy2DAsync(d.X, Dp * 4, target->X, (size_t)d.D * 4, (size_t)d.D * 4, (size_t)d.N,
                                      hipMemcpyDeviceToDevice, job->stream));
-    HIP_TRY_JOB(ess_prior_draw(d, x0, job->stream));
-    job->launches += x0 ? 2 : 3;
+        HIP_TRY_JOB(hipMemcpyAsync(d.y, target->y, (size_t)d.N * 4, hipMemcpyDeviceToDevice, job->stream));
+        hipLaunchKernelGGL(fill_i32_kernel, dim3((d.m + 255) / 256), dim3(256), 0, job->stream, d.k, 1, d.m);
+        HIP_TRY_JOB(hipGetLastError());
+        HIP_TRY_JOB(nuts_init_state(d, x0, job->stream));
+        job->launches += 3;
+    }
     *out = job;
     return FSMMC_OK;
 }
@@ -378,11 +422,52 @@ static fsmmc_status progress(fsmmc_job* job, std::vector<uint32_t>& t, std::vect
     return FSMMC_OK;
 }
 
+// NUTS runtime: steps of {transition, compaction, gradient, reduce}, issued in
+// batches; after each batch the host reads how many chains are still alive
+// and how many asked for a gradient in the last step.
+static fsmmc_status nuts_run(fsmmc_job* job, int mode, int64_t max_steps, uint32_t tstop, int32_t* all_done)
+{
+    JobDev& d = job->d;
+    d.tstop = tstop;
+    const int64_t b = max_steps > 0 ? max_steps : INT64_MAX;
+    hipLaunchKernelGGL(fill_i64_kernel, dim3((d.m + 255) / 256), dim3(256), 0, job->stream, d.budget, b, d.m);
+    HIP_TRY(hipGetLastError());
+    job->launches++;
+    const int batch = 16;
+    uint32_t* h = reinterpret_cast<uint32_t*>(job->h_ctr + 8);
+    uint32_t alive = 1;
+    for (;;) {
+        for (int i = 0; i < batch; ++i) {
+            const uint32_t s = job->step;
+            HIP_TRY(launch(job, mode == 0 ? KC_FSM : KC_SYNC, [&] { return nuts_transition(d, mode, s, job->stream); }));
+            HIP_TRY(launch(job, KC_G, [&] { return nuts_gradient(d, job->stream); }));
+            job->step++;
+        }
+        HIP_TRY(hipMemcpyAsync(h, d.wctr, 6 * 4, hipMemcpyDeviceToHost, job->stream));
+        HIP_TRY(hipMemcpyAsync(h + 6, d.count, 4, hipMemcpyDeviceToHost, job->stream));
+        HIP_TRY(hipStreamSynchronize(job->stream));
+        harvest(job);
+        alive = h[3 + (job->step - 1) % 3];
+        const uint32_t reqs = h[6];
+        if (alive == 0) break;
+        if (mode == 0 && reqs == 0) break;  // every live chain has spent its budget
+    }
+    if (all_done) {
+        std::vector<uint32_t> t(d.m);
+        HIP_TRY(hipMemcpy(t.data(), d.t, t.size() * 4, hipMemcpyDeviceToHost));
+        int done = 1;
+        for (uint32_t v : t) done &= v >= (uint32_t)d.n;
+        *all_done = done;
+    }
+    return FSMMC_OK;
+}
+
 fsmmc_status fsmmc_step_fsm(fsmmc_job* job, int64_t max_steps, int32_t* all_done)
 {
     if (!job) return fail(FSMMC_EINVAL, "job is NULL");
     JobDev& d = job->d;
     HIP_TRY(hipSetDevice(job->ctx->device));
+    if (d.kind == FSMMC_NUTS) return nuts_run(job, 0, max_steps, (uint32_t)d.n, all_done);
     const int64_t b = max_steps > 0 ? max_steps : INT64_MAX;
     hipLaunchKernelGGL(fill_i64_kernel, dim3((d.m + 255) / 256), dim3(256), 0, job->stream, d.budget, b, d.m);
     HIP_TRY(hipGetLastError());
@@ -416,6 +501,13 @@ fsmmc_status fsmmc_step_synchronized(fsmmc_job* job, int32_t n_draws, int32_t mo
         if (t[i] != t0 || k[i] != 1)
             return fail(FSMMC_EINVAL, "chains are not synchronized at a draw boundary");
     const uint32_t t1 = std::min<uint32_t>((uint32_t)d.n, t0 + (uint32_t)std::max(n_draws, 0));
+    if (d.kind == FSMMC_NUTS) {
+        if (t1 == t0) {
+            if (all_done) *all_done = t1 >= (uint32_t)d.n ? 1 : 0;
+            return FSMMC_OK;
+        }
+        return nuts_run(job, mode == FSMMC_SYNC_VMAP ? 1 : 2, 0, t1, all_done);
+    }
     uint32_t wstart = t0;
     for (uint32_t dr = t0; dr < t1; ++dr) {
         if (dr == t0 || dr - wstart == (uint32_t)d.W) {
@@ -458,6 +550,35 @@ fsmmc_status fsmmc_collect_counts(fsmmc_job* job, int32_t* dst)
     HIP_TRY(hipMemcpyAsync(dst, job->d.counts, (size_t)job->d.m * job->d.n * 4, hipMemcpyDeviceToHost,
                            job->stream));
     HIP_TRY(hipStreamSynchronize(job->stream));
+    return FSMMC_OK;
+}
+
+fsmmc_status fsmmc_eval_potential(fsmmc_job* job, int32_t n_points, const void* theta, void* grad, void* U)
+{
+    if (!job || !theta || !U) return fail(FSMMC_EINVAL, "job, theta or U is NULL");
+    JobDev& d = job->d;
+    if (d.kind != FSMMC_NUTS) return fail(FSMMC_ENOTSUP, "only NUTS jobs evaluate a potential");
+    if (n_points < 1 || n_points > d.m) return fail(FSMMC_EINVAL, "n_points must be in [1, n_chains]");
+    HIP_TRY(hipSetDevice(job->ctx->device));
+    // The positions go through the request buffer, which only the gradient
+    // kernels read; results land in temporary buffers so the gradients of
+    // chains with a leapfrog in flight are kept.
+    void *tg = nullptr, *tu = nullptr;
+    HIP_TRY(hipMalloc(&tg, (size_t)n_points * d.Dp * 4));
+    hipError_t e = hipMalloc(&tu, (size_t)n_points * 4);
+    if (e == hipSuccess) e = hipMemsetAsync(d.Thq, 0, (size_t)d.m * d.Dp * 4, job->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(d.Thq, (size_t)d.Dp * 4, theta, (size_t)d.D * 4, (size_t)d.D * 4, (size_t)n_points,
+                             hipMemcpyDeviceToDevice, job->stream);
+    if (e == hipSuccess) e = nuts_gradient_dense(d, n_points, (float*)tg, (float*)tu, d.Dp, job->stream);
+    if (e == hipSuccess && grad)
+        e = hipMemcpy2DAsync(grad, (size_t)d.D * 4, tg, (size_t)d.Dp * 4, (size_t)d.D * 4, (size_t)n_points,
+                             hipMemcpyDeviceToDevice, job->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(U, tu, (size_t)n_points * 4, hipMemcpyDeviceToDevice, job->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(job->stream);
+    (void)hipFree(tg);
+    if (tu) (void)hipFree(tu);
+    if (e != hipSuccess) return hip_fail(e, "fsmmc_eval_potential");
     return FSMMC_OK;
 }
 

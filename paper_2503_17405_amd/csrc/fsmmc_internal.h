@@ -50,6 +50,29 @@ struct JobDev {
     void* nu = nullptr;  // m x W x Dp ellipse directions of the current window
     int W = 0;
 
+    // NUTS
+    int32_t* jd = nullptr;     // tree depth of the subtree being built
+    int32_t* vdir = nullptr;   // direction of the subtree (+1 / -1)
+    int32_t* nn = nullptr;     // leaves done in the subtree
+    int32_t* flags = nullptr;  // invalid / stop / diverged / turned / pending bits
+    void* H0 = nullptr;        // initial Hamiltonian of the draw
+    void* Wsum = nullptr;      // log-sum of leaf weights of the tree
+    void* Wsub = nullptr;      // log-sum of leaf weights of the subtree
+    void* US = nullptr;        // potential at the subtree proposal
+    void* V = nullptr;         // m x nvec x Dp vector state
+    int nvec = 0;
+    void* Thq = nullptr;       // m x Dp positions whose gradient is requested
+    void* Gres = nullptr;      // m x Dp gradients returned
+    void* Ures = nullptr;      // m potentials returned
+    int32_t* req = nullptr;    // m request flags
+    int32_t* list = nullptr;   // m compacted requests
+    int32_t* count = nullptr;  // 1
+    void* Gpart = nullptr;     // nslices x m x Dp
+    void* Upart = nullptr;     // nslices x m
+    uint32_t* wctr = nullptr;  // [0..2] chains still in their draw, [3..5] chains alive (per step mod 3)
+    int slice_rows = 0, nslices = 0;
+    uint32_t tstop = 0;        // chains stop at this draw count
+
     // outputs
     void* out = nullptr;  // m x n x D
     int32_t* counts = nullptr;  // m x n
@@ -68,5 +91,12 @@ hipError_t ess_fsm_round(const JobDev& j, hipStream_t s);
 hipError_t ess_sync_draw(const JobDev& j, uint32_t draw, uint32_t slot, hipStream_t s);
 hipError_t ess_pad_draw(const JobDev& j, uint32_t draw, uint32_t slot, hipStream_t s);
 int ess_supported_epl(int D, int dtype);
+
+// NUTS launchers (nuts.hip); mode 0 = FSM, 1 = synchronized vmap, 2 = synchronized compact
+int nuts_nvec(int max_depth);
+hipError_t nuts_init_state(const JobDev& j, const void* x0, hipStream_t s);
+hipError_t nuts_transition(const JobDev& j, int mode, uint32_t step, hipStream_t s);
+hipError_t nuts_gradient(const JobDev& j, hipStream_t s);
+hipError_t nuts_gradient_dense(const JobDev& j, int ncols, float* Gout, float* Uout, int gstride, hipStream_t s);
 
 }  // namespace fsmmc

@@ -26,7 +26,7 @@ EXPORTS = [
     "fsmmc_ctx_create", "fsmmc_ctx_destroy", "fsmmc_ctx_bytes_in_use", "fsmmc_init_chains",
     "fsmmc_step_fsm", "fsmmc_step_synchronized", "fsmmc_collect_samples", "fsmmc_collect_counts",
     "fsmmc_chain_progress", "fsmmc_job_stats", "fsmmc_job_sync", "fsmmc_job_free",
-    "fsmmc_last_error", "fsmmc_version",
+    "fsmmc_last_error", "fsmmc_version", "fsmmc_eval_potential",
 ]
 
 
@@ -81,6 +81,7 @@ def _load():
         "fsmmc_collect_samples": ([p, i32, i32, p, i32], C.c_int),
         "fsmmc_collect_counts": ([p, p], C.c_int),
         "fsmmc_chain_progress": ([p, p], C.c_int),
+        "fsmmc_eval_potential": ([p, i32, p, p, p], C.c_int),
         "fsmmc_job_stats": ([p, p], C.c_int),
         "fsmmc_job_sync": ([p], C.c_int),
         "fsmmc_job_free": ([p], C.c_int),
@@ -106,7 +107,15 @@ def version():
 
 
 def _ptr(t):
-    return None if t is None else C.c_void_p(t.data_ptr())
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("fsmmc needs contiguous row-major tensors (call .contiguous())")
+    return C.c_void_p(t.data_ptr())
+
+
+def _dense(t):
+    return None if t is None else t.contiguous()
 
 
 def _stream_ptr(stream):
@@ -161,6 +170,10 @@ def fsmmc_chain_progress(job, dst):
     _check(lib.fsmmc_chain_progress(job, C.c_void_p(dst.ctypes.data)))
 
 
+def fsmmc_eval_potential(job, theta, grad, U):
+    _check(lib.fsmmc_eval_potential(job, int(theta.shape[0]), _ptr(theta), _ptr(grad), _ptr(U)))
+
+
 def fsmmc_job_stats(job):
     s = Stats()
     _check(lib.fsmmc_job_stats(job, C.byref(s)))
@@ -193,6 +206,7 @@ class Context:
 def gp_target(chol_L, y, noise_sd=None):
     """Target spec of a latent GP (tensors on the device, in the job dtype)."""
     kind = GP_LOGISTIC if noise_sd is None else GP_GAUSS
+    chol_L, y = _dense(chol_L), _dense(y)
     spec = TargetSpec(kind, int(y.numel()), 0, 0, None, _ptr(y), _ptr(chol_L), None,
                       float(noise_sd or 0.0))
     return spec, (chol_L, y)
@@ -200,6 +214,17 @@ def gp_target(chol_L, y, noise_sd=None):
 
 def ess_sampler(dtype=F32):
     return SamplerSpec(ESS, dtype, 0, 0, 0.0, (C.c_double * 4)())
+
+
+def logreg_target(X, y):
+    """Bayesian logistic regression with a N(0, I) prior: X (N x D), labels y (N,)."""
+    X, y = _dense(X), _dense(y)
+    spec = TargetSpec(LOGREG, int(X.shape[1]), int(X.shape[0]), 0, _ptr(X), _ptr(y), None, None, 0.0)
+    return spec, (X, y)
+
+
+def nuts_sampler(step_size, max_depth=10, dtype=F32):
+    return SamplerSpec(NUTS, dtype, int(max_depth), 0, float(step_size), (C.c_double * 4)())
 
 
 class Job:
@@ -214,8 +239,12 @@ class Job:
         self.dtype = torch.float32 if sampler.dtype == F32 else torch.float64
         tune = Tune(window, 1 if timing else 0) if (window or timing) else None
         torch.cuda.synchronize()
-        self.handle = fsmmc_init_chains(ctx.handle, spec, sampler, n_chains, n_draws, seed, x0, out,
-                                        stream, tune)
+        # x0 is read asynchronously on the job's stream: keep a dense copy alive with the job
+        self._x0 = _dense(x0)
+        if out is not None and not out.is_contiguous():
+            raise ValueError("out must be a contiguous (n_chains, n_draws, dim) tensor")
+        self.handle = fsmmc_init_chains(ctx.handle, spec, sampler, n_chains, n_draws, seed, self._x0,
+                                        out, stream, tune)
         self.out = out
 
     def step_fsm(self, max_steps=0):
@@ -243,6 +272,15 @@ class Job:
 
     def stats(self):
         return fsmmc_job_stats(self.handle)
+
+    def potential(self, theta):
+        """U and grad U of the job's target at theta (device tensor, points x dim)."""
+        import torch
+        theta = theta.contiguous()
+        g = torch.empty_like(theta)
+        U = torch.empty(theta.shape[0], dtype=theta.dtype, device=theta.device)
+        fsmmc_eval_potential(self.handle, theta, g, U)
+        return U, g
 
     def sync(self):
         fsmmc_job_sync(self.handle)

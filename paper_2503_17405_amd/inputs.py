@@ -86,7 +86,7 @@ def logreg_laplace(X, y, n_chains, seed, iters=50):
     Z = g.standard_normal((n_chains, D))
     # beta0 = b + H^{-1/2} z with H = Lh Lh^T  ->  solve Lh^T w = z
     W = np.linalg.solve(Lh.T, Z.T).T
-    return dict(map=b, hessian=H, x0=b[None, :] + W)
+    return dict(map=b, hessian=H, x0=np.ascontiguousarray(b[None, :] + W))
 
 
 def ess_uneven_targets(n_targets=32, dmin=64, dmax=1024, mmin=256, mmax=2048, nmin=200,
