@@ -259,7 +259,19 @@ static fsmmc_status validate(const fsmmc_target_spec* t, const fsmmc_sampler_spe
             return fail(FSMMC_EINVAL, "step_size must be > 0");
         return FSMMC_OK;
     }
-    if (s->kind == FSMMC_DRMH) return fail(FSMMC_ENOTSUP, "sampler not built into this library version");
+    if (s->kind == FSMMC_DRMH) {
+        if (t->kind != FSMMC_FUNNEL && t->kind != FSMMC_GAUSS_DIAG)
+            return fail(FSMMC_ENOTSUP, "DRMH is built for FUNNEL and GAUSS_DIAG targets");
+        if (s->dtype != FSMMC_F32) return fail(FSMMC_ENOTSUP, "DRMH is built for FP32");
+        if (t->dim > dr_max_dim()) return fail(FSMMC_ENOTSUP, "DRMH dim must be <= 16");
+        if (t->kind == FSMMC_FUNNEL && t->dim < 2) return fail(FSMMC_EINVAL, "FUNNEL needs dim >= 2");
+        if (t->kind == FSMMC_GAUSS_DIAG && !t->prec) return fail(FSMMC_EINVAL, "GAUSS_DIAG needs prec");
+        if (s->n_stages < 1 || s->n_stages > 3) return fail(FSMMC_EINVAL, "n_stages must be in [1, 3]");
+        for (int i = 0; i < s->n_stages; ++i)
+            if (!(s->scales[i] > 0.0) || !std::isfinite(s->scales[i]))
+                return fail(FSMMC_EINVAL, "proposal scales must be > 0");
+        return FSMMC_OK;
+    }
     return fail(FSMMC_EINVAL, "unknown sampler kind");
 }
 
@@ -360,6 +372,21 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
                                          hipMemcpyDeviceToDevice, job->stream));
         HIP_TRY_JOB(ess_prior_draw(d, x0, job->stream));
         job->launches += x0 ? 2 : 3;
+    } else if (d.kind == FSMMC_DRMH) {  // lane per chain, [d][chain] state
+        d.Dp = d.D;
+        ALLOC(d.x, m * (size_t)d.D * 4);
+        ALLOC(d.V, 2 * m * (size_t)d.D * 4);
+        ALLOC(d.H0, m * 4);
+        ALLOC(d.Wsum, m * 4);
+        ALLOC(d.maxN, (size_t)d.n * 4);
+        ALLOC(d.sink, m * 4);
+        ALLOC(d.prec, (size_t)d.D * 4);
+        if (target->kind == FSMMC_GAUSS_DIAG)
+            HIP_TRY_JOB(hipMemcpyAsync(d.prec, target->prec, (size_t)d.D * 4, hipMemcpyDeviceToDevice, job->stream));
+        hipLaunchKernelGGL(fill_i32_kernel, dim3((d.m + 255) / 256), dim3(256), 0, job->stream, d.k, 1, d.m);
+        HIP_TRY_JOB(hipGetLastError());
+        HIP_TRY_JOB(dr_init_state(d, x0, job->stream));
+        job->launches += x0 ? 3 : 2;
     } else {  // NUTS on logistic regression
         d.EPL = d.D <= 64 ? 1 : 2;
         d.Dp = 64 * d.EPL;
@@ -468,6 +495,20 @@ fsmmc_status fsmmc_step_fsm(fsmmc_job* job, int64_t max_steps, int32_t* all_done
     JobDev& d = job->d;
     HIP_TRY(hipSetDevice(job->ctx->device));
     if (d.kind == FSMMC_NUTS) return nuts_run(job, 0, max_steps, (uint32_t)d.n, all_done);
+    if (d.kind == FSMMC_DRMH) {
+        // one persistent launch: every lane runs its chain to n draws or to its budget
+        d.tstop = (uint32_t)d.n;
+        const int64_t b = max_steps > 0 ? max_steps : INT64_MAX;
+        hipLaunchKernelGGL(fill_i64_kernel, dim3((d.m + 255) / 256), dim3(256), 0, job->stream, d.budget, b, d.m);
+        HIP_TRY(hipGetLastError());
+        job->launches++;
+        HIP_TRY(hipMemsetAsync(d.ctr + 3, 0, 2 * sizeof(unsigned long long), job->stream));
+        HIP_TRY(launch(job, KC_FSM, [&] { return dr_fsm_round(d, job->stream); }));
+        fsmmc_status s = read_ctr(job);
+        if (s != FSMMC_OK) return s;
+        if (all_done) *all_done = job->h_ctr[4] == 0 ? 1 : 0;
+        return FSMMC_OK;
+    }
     const int64_t b = max_steps > 0 ? max_steps : INT64_MAX;
     hipLaunchKernelGGL(fill_i64_kernel, dim3((d.m + 255) / 256), dim3(256), 0, job->stream, d.budget, b, d.m);
     HIP_TRY(hipGetLastError());
@@ -496,6 +537,10 @@ fsmmc_status fsmmc_step_synchronized(fsmmc_job* job, int32_t n_draws, int32_t mo
     std::vector<int32_t> k;
     fsmmc_status s = progress(job, t, &k);
     if (s != FSMMC_OK) return s;
+    if (d.kind == FSMMC_DRMH) {  // the stage counter marks a draw in progress
+        HIP_TRY(hipMemcpy(k.data(), d.evals, k.size() * 4, hipMemcpyDeviceToHost));
+        for (int32_t& v : k) v = v == 0 ? 1 : 0;
+    }
     const uint32_t t0 = t[0];
     for (int i = 0; i < d.m; ++i)
         if (t[i] != t0 || k[i] != 1)
@@ -507,6 +552,17 @@ fsmmc_status fsmmc_step_synchronized(fsmmc_job* job, int32_t n_draws, int32_t mo
             return FSMMC_OK;
         }
         return nuts_run(job, mode == FSMMC_SYNC_VMAP ? 1 : 2, 0, t1, all_done);
+    }
+    if (d.kind == FSMMC_DRMH) {
+        for (uint32_t dr = t0; dr < t1; ++dr) {
+            HIP_TRY(launch(job, KC_SYNC, [&] { return dr_sync_draw(d, dr, job->stream); }));
+            if (mode == FSMMC_SYNC_VMAP)
+                HIP_TRY(launch(job, KC_PAD, [&] { return dr_pad_draw(d, dr, job->stream); }));
+        }
+        HIP_TRY(hipStreamSynchronize(job->stream));
+        harvest(job);
+        if (all_done) *all_done = t1 >= (uint32_t)d.n ? 1 : 0;
+        return FSMMC_OK;
     }
     uint32_t wstart = t0;
     for (uint32_t dr = t0; dr < t1; ++dr) {

@@ -99,4 +99,11 @@ hipError_t nuts_transition(const JobDev& j, int mode, uint32_t step, hipStream_t
 hipError_t nuts_gradient(const JobDev& j, hipStream_t s);
 hipError_t nuts_gradient_dense(const JobDev& j, int ncols, float* Gout, float* Uout, int gstride, hipStream_t s);
 
+// DR launchers (dr.hip)
+int dr_max_dim();
+hipError_t dr_init_state(const JobDev& j, const void* x0, hipStream_t s);
+hipError_t dr_fsm_round(const JobDev& j, hipStream_t s);
+hipError_t dr_sync_draw(const JobDev& j, uint32_t draw, hipStream_t s);
+hipError_t dr_pad_draw(const JobDev& j, uint32_t draw, hipStream_t s);
+
 }  // namespace fsmmc

@@ -227,6 +227,22 @@ def nuts_sampler(step_size, max_depth=10, dtype=F32):
     return SamplerSpec(NUTS, dtype, int(max_depth), 0, float(step_size), (C.c_double * 4)())
 
 
+def funnel_target(dim=10):
+    """Neal's funnel: v ~ N(0, 9), x_i | v ~ N(0, e^v), i = 1 .. dim-1."""
+    return TargetSpec(FUNNEL, int(dim), 0, 0, None, None, None, None, 0.0), ()
+
+
+def gauss_target(prec):
+    """N(0, diag(prec)^-1); prec is a device tensor of precisions."""
+    prec = _dense(prec)
+    return TargetSpec(GAUSS_DIAG, int(prec.numel()), 0, 0, None, None, None, _ptr(prec), 0.0), (prec,)
+
+
+def dr_sampler(scales=(1.0, 0.3, 0.1), dtype=F32):
+    sc = list(scales) + [0.0] * (4 - len(scales))
+    return SamplerSpec(DRMH, dtype, 0, len(scales), 0.0, (C.c_double * 4)(*sc))
+
+
 class Job:
     """One sampling job: n_chains chains x n_draws draws of one target."""
 

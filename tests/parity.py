@@ -71,6 +71,41 @@ def is_near_tie(margin, terms, eps=EPS32):
     return margin < 64 * eps * (1.0 + terms)
 
 
+def _lq(a, b, sc):
+    r = b - a
+    return -float(r @ r) / (2.0 * sc * sc)
+
+
+def dr_flip_near_tie(target, scales, n_stages, seed, chain, draw, x_prev, eps=EPS32):
+    """Smallest relative margin of the oracle's DR acceptance decisions in one
+    draw from x_prev (stages walked as the oracle walks them)."""
+    D = target.dim
+    lx = O.logpdf(target, x_prev)
+    ys, ls, rel = [], [], []
+    for s in range(n_stages):
+        y = x_prev + scales[s] * O.normals(seed, chain, draw, O.ROLE_PROP, s, D)
+        ly = O.logpdf(target, y)
+        ys.append(y)
+        ls.append(ly)
+        if s == 0:
+            la, qs = O.dr_log_alpha1(lx, ly), []
+        elif s == 1:
+            qs = [_lq(x_prev, ys[0], scales[0]), _lq(y, ys[0], scales[0])]
+            la = O.dr_log_alpha2(lx, ls[0], ly, *qs)
+        else:
+            qs = [_lq(x_prev, ys[0], scales[0]), _lq(ys[1], ys[0], scales[0]), _lq(x_prev, ys[1], scales[1]),
+                  _lq(y, ys[1], scales[0]), _lq(y, ys[0], scales[1]), _lq(ys[0], ys[1], scales[0])]
+            la = O.dr_log_alpha3(lx, ls[0], ls[1], ly, qs)
+        lu = np.log(O.uniform(seed, chain, draw, O.ROLE_ACC, s))
+        scale = abs(lx) + sum(abs(v) for v in ls) + sum(abs(q) for q in qs)
+        if np.isfinite(la):
+            rel.append(abs(lu - la) / (1.0 + scale))
+        if lu < la:
+            break
+    r = min(rel) if rel else np.inf
+    return r < 64 * eps, r
+
+
 def nuts_flip_near_tie(target, eps_step, max_depth, seed, chain, draw, x_prev, eps=EPS32):
     """Smallest relative decision margin of the oracle's NUTS draw from x_prev,
     and whether it is a near-tie."""
