@@ -141,6 +141,32 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// A D-vector held by one wave: element d = e * 64 + lane.
+template <int EPL>
+struct WaveVec {
+    float r[EPL];
+    __device__ __forceinline__ void load(const float* p, int lane)
+    {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) r[e] = p[e * 64 + lane];
+    }
+    __device__ __forceinline__ void store(float* p, int lane) const
+    {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) p[e * 64 + lane] = r[e];
+    }
+};
+
+// Dot product of two wave vectors (lane-local sum over e, then the butterfly).
+template <int EPL>
+__device__ __forceinline__ float wdot(const WaveVec<EPL>& a, const WaveVec<EPL>& b)
+{
+    float s = 0.0f;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) s += a.r[e] * b.r[e];
+    return wave_sum(s);
+}
+
 // ---------------------------------------------------------------- math
 template <typename T>
 struct M;

@@ -63,30 +63,6 @@ struct NutsK {
     uint32_t* wctr;
 };
 
-template <int EPL>
-struct WaveVec {
-    float r[EPL];
-    __device__ __forceinline__ void load(const float* p, int lane)
-    {
-#pragma unroll
-        for (int e = 0; e < EPL; ++e) r[e] = p[e * 64 + lane];
-    }
-    __device__ __forceinline__ void store(float* p, int lane) const
-    {
-#pragma unroll
-        for (int e = 0; e < EPL; ++e) p[e * 64 + lane] = r[e];
-    }
-};
-
-template <int EPL>
-__device__ __forceinline__ float wdot(const WaveVec<EPL>& a, const WaveVec<EPL>& b)
-{
-    float s = 0.0f;
-#pragma unroll
-    for (int e = 0; e < EPL; ++e) s += a.r[e] * b.r[e];
-    return wave_sum(s);
-}
-
 enum { V_THL = 0, V_PL, V_GL, V_THR, V_PR, V_GR, V_THP, V_GP, V_THS, V_GS, V_RHO, V_RHOS, V_PH, V_FIXED };
 
 template <int EPL>
@@ -343,176 +319,6 @@ __global__ __launch_bounds__(1024) void nuts_compact_kernel(const int32_t* req, 
     if (tid == 0) *count = total;
 }
 
-struct GradK {
-    int m, N, Dp, slice_rows, nslices, dense;  // dense > 0: columns are chains 0 .. dense-1
-    const float* X;  // Np x Dp
-    const float* y;  // Np
-    const float* Th; // m x Dp, indexed by chain
-    const int32_t* list;
-    const int32_t* count;
-    float* Gpart;    // nslices x m x Dp
-    float* Upart;    // nslices x m
-};
-
-// Block: 4 waves, 64 listed chains, one slice of rows.  Each wave walks row
-// chunks of 32: eta (32 x 64) = X_chunk Theta^T on MFMA, r = y - sigmoid(eta)
-// in place, then X_chunk^T r accumulated into DT x 2 tiles of 32 x 32.  The
-// second product takes its B operand straight from the first product's
-// accumulator registers: at k-step s a lane contributes the row its own
-// register s holds.  The four waves' partials are added in LDS in wave order.
-template <int DT>
-__global__ __launch_bounds__(256) void logreg_grad_kernel(GradK a)
-{
-    constexpr int DP = 32 * DT;
-    __shared__ float Ths[64 * (DP + 1)];
-    __shared__ float Ured[64];
-    __shared__ int cols[64];
-    const int ncols = a.dense > 0 ? a.dense : *a.count;
-    const int ct = blockIdx.x, sl = blockIdx.y;
-    if (ct * 64 >= ncols) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, l32 = lane & 31;
-    if (tid < 64) {
-        const int g = ct * 64 + tid;
-        cols[tid] = g < ncols ? (a.dense > 0 ? g : a.list[g]) : -1;
-        Ured[tid] = 0.0f;
-    }
-    __syncthreads();
-    for (int i = tid; i < 64 * DP; i += 256) {
-        const int col = i / DP, d = i - col * DP;
-        const int ch = cols[col];
-        Ths[col * (DP + 1) + d] = ch >= 0 ? a.Th[(size_t)ch * DP + d] : 0.0f;
-    }
-    __syncthreads();
-
-    floatx16 accg[DT][2];
-#pragma unroll
-    for (int dt = 0; dt < DT; ++dt)
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int q = 0; q < 16; ++q) accg[dt][c][q] = 0.0f;
-    float uacc[2] = {0.0f, 0.0f};
-
-    const int rb = sl * a.slice_rows, re = min(rb + a.slice_rows, a.N);
-    for (int r0 = rb + wave * 32; r0 < re; r0 += 128) {
-        floatx16 eta[2];
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int q = 0; q < 16; ++q) eta[c][q] = 0.0f;
-        const float* xr = a.X + (size_t)(r0 + l32) * DP + h * (DP / 2);
-#pragma unroll 4
-        for (int kb = 0; kb < DP / 2; kb += 4) {
-            const float4 xv = *reinterpret_cast<const float4*>(xr + kb);
-            const float xa[4] = {xv.x, xv.y, xv.z, xv.w};
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int d = h * (DP / 2) + kb + i;
-#pragma unroll
-                for (int c = 0; c < 2; ++c)
-                    eta[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(xa[i], Ths[(c * 32 + l32) * (DP + 1) + d],
-                                                                 eta[c], 0, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int row = r0 + 8 * (q >> 2) + 4 * h + (q & 3);
-                const float e = eta[c][q];
-                const bool ok = row < a.N;
-                const float yv = a.y[row];
-                const float ex = expf(-fabsf(e));
-                const float sig = e >= 0.0f ? 1.0f / (1.0f + ex) : ex / (1.0f + ex);
-                const float sp = fmaxf(e, 0.0f) + log1pf(ex);
-                uacc[c] += ok ? (yv * e - sp) : 0.0f;
-                eta[c][q] = ok ? (yv - sig) : 0.0f;
-            }
-        }
-#pragma unroll
-        for (int dt = 0; dt < DT; ++dt) {
-#pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                const int row = r0 + 8 * (s >> 2) + 4 * h + (s & 3);
-                const float xa = a.X[(size_t)row * DP + dt * 32 + l32];
-#pragma unroll
-                for (int c = 0; c < 2; ++c)
-                    accg[dt][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(xa, eta[c][s], accg[dt][c], 0, 0, 0);
-            }
-        }
-    }
-    // per-column log-likelihood of this wave: both lane halves hold half the rows
-#pragma unroll
-    for (int c = 0; c < 2; ++c) uacc[c] += __shfl_xor(uacc[c], 32, 64);
-    __syncthreads();
-    float* Red = Ths;  // DP x 64, reused
-    for (int w = 0; w < 4; ++w) {
-        if (wave == w) {
-#pragma unroll
-            for (int dt = 0; dt < DT; ++dt)
-#pragma unroll
-                for (int c = 0; c < 2; ++c)
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) {
-                        const int d = dt * 32 + 8 * (q >> 2) + 4 * h + (q & 3);
-                        const int col = c * 32 + l32;
-                        float* cell = &Red[d * 64 + col];
-                        *cell = (w == 0) ? accg[dt][c][q] : *cell + accg[dt][c][q];
-                    }
-            if (h == 0) {
-#pragma unroll
-                for (int c = 0; c < 2; ++c) Ured[c * 32 + l32] += uacc[c];
-            }
-        }
-        __syncthreads();
-    }
-    for (int i = tid; i < 64 * DP; i += 256) {
-        const int col = i / DP, d = i - col * DP;
-        const int ch = cols[col];
-        if (ch >= 0) a.Gpart[((size_t)sl * a.m + ch) * DP + d] = Red[d * 64 + col];
-    }
-    if (tid < 64 && cols[tid] >= 0) a.Upart[(size_t)sl * a.m + cols[tid]] = Ured[tid];
-}
-
-struct ReduceK {
-    int m, Dp, nslices, dense;  // dense > 0: columns are chains 0 .. dense-1
-    const float* Th;
-    const int32_t* list;
-    const int32_t* count;
-    const float* Gpart;
-    const float* Upart;
-    float* G;  // chain-indexed outputs, row stride gstride
-    float* U;
-    int gstride;
-};
-
-// grad U = theta - sum_s partial_s, U = |theta|^2/2 - sum_s loglik_s (slice order).
-template <int EPL>
-__global__ __launch_bounds__(256) void logreg_reduce_kernel(ReduceK a)
-{
-    const int lane = threadIdx.x & 63;
-    const int p = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
-    const int ncols = a.dense > 0 ? a.dense : *a.count;
-    if (p >= ncols) return;
-    const int c = a.dense > 0 ? p : a.list[p];
-    WaveVec<EPL> th, g;
-    th.load(a.Th + (size_t)c * a.Dp, lane);
-#pragma unroll
-    for (int e = 0; e < EPL; ++e) g.r[e] = 0.0f;
-    for (int s = 0; s < a.nslices; ++s) {
-        const float* gp = a.Gpart + ((size_t)s * a.m + c) * a.Dp;
-#pragma unroll
-        for (int e = 0; e < EPL; ++e) g.r[e] += gp[e * 64 + lane];
-    }
-#pragma unroll
-    for (int e = 0; e < EPL; ++e) g.r[e] = th.r[e] - g.r[e];
-    g.store(a.G + (size_t)c * a.gstride, lane);
-    float ll = 0.0f;
-    for (int s = 0; s < a.nslices; ++s) ll += a.Upart[(size_t)s * a.m + c];
-    const float U = 0.5f * wdot(th, th) - ll;
-    if (lane == 0) a.U[c] = U;
-}
-
 // Default start: theta0 ~ N(0, I) from the INIT stream (into both buffers).
 __global__ void nuts_normal_init_kernel(float* thp, int vstride, float* thq, int m, int D, int Dp, uint64_t seed)
 {
@@ -568,52 +374,6 @@ static NutsK nuts_view(const JobDev& j, int mode, uint32_t step)
 
 int nuts_nvec(int max_depth) { return V_FIXED + 2 * max_depth; }
 
-static hipError_t grad_launch(const JobDev& j, int dense, float* Gout, float* Uout, int gstride, hipStream_t s)
-{
-    GradK g;
-    g.m = j.m;
-    g.N = j.N;
-    g.Dp = j.Dp;
-    g.slice_rows = j.slice_rows;
-    g.nslices = j.nslices;
-    g.dense = dense;
-    g.X = (const float*)j.X;
-    g.y = (const float*)j.y;
-    g.Th = (const float*)j.Thq;
-    g.list = j.list;
-    g.count = j.count;
-    g.Gpart = (float*)j.Gpart;
-    g.Upart = (float*)j.Upart;
-    const dim3 grid((j.m + 63) / 64, j.nslices), block(256);
-    switch (j.Dp / 32) {
-    case 1: hipLaunchKernelGGL(logreg_grad_kernel<1>, grid, block, 0, s, g); break;
-    case 2: hipLaunchKernelGGL(logreg_grad_kernel<2>, grid, block, 0, s, g); break;
-    case 4: hipLaunchKernelGGL(logreg_grad_kernel<4>, grid, block, 0, s, g); break;
-    default: return hipErrorInvalidValue;
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    ReduceK r;
-    r.m = j.m;
-    r.Dp = j.Dp;
-    r.nslices = j.nslices;
-    r.dense = dense;
-    r.Th = (const float*)j.Thq;
-    r.list = j.list;
-    r.count = j.count;
-    r.Gpart = (const float*)j.Gpart;
-    r.Upart = (const float*)j.Upart;
-    r.G = Gout;
-    r.U = Uout;
-    r.gstride = gstride;
-    const dim3 rg((j.m + 3) / 4);
-    if (j.Dp <= 64)
-        hipLaunchKernelGGL(logreg_reduce_kernel<1>, rg, dim3(256), 0, s, r);
-    else
-        hipLaunchKernelGGL(logreg_reduce_kernel<2>, rg, dim3(256), 0, s, r);
-    return hipGetLastError();
-}
-
 hipError_t nuts_init_state(const JobDev& j, const void* x0, hipStream_t s)
 {
     float* thp = (float*)j.V + (size_t)V_THP * j.Dp;
@@ -634,7 +394,7 @@ hipError_t nuts_init_state(const JobDev& j, const void* x0, hipStream_t s)
     }
     // grad U and U at the start, straight into the proposal slots (gP, UP)
     float* gp = (float*)j.V + (size_t)V_GP * j.Dp;
-    return grad_launch(j, j.m, gp, (float*)j.lx, vstride, s);
+    return nuts_gradient_dense(j, j.m, gp, (float*)j.lx, vstride, s);
 }
 
 hipError_t nuts_transition(const JobDev& j, int mode, uint32_t step, hipStream_t s)
@@ -652,16 +412,4 @@ hipError_t nuts_transition(const JobDev& j, int mode, uint32_t step, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t nuts_gradient(const JobDev& j, hipStream_t s)
-{
-    return grad_launch(j, 0, (float*)j.Gres, (float*)j.Ures, j.Dp, s);
-}
-
-}  // namespace fsmmc
-
-namespace fsmmc {
-hipError_t nuts_gradient_dense(const JobDev& j, int ncols, float* Gout, float* Uout, int gstride, hipStream_t s)
-{
-    return grad_launch(j, ncols, Gout, Uout, gstride, s);
-}
 }  // namespace fsmmc
