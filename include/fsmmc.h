@@ -214,6 +214,71 @@ fsmmc_status fsmmc_job_sync(fsmmc_job* job);
 /* Release a job and its device memory (waits for its queued work first). */
 fsmmc_status fsmmc_job_free(fsmmc_job* job);
 
+/* ---------------------------------------------------------------- batching
+ * A batch steps several jobs together, possibly of different samplers,
+ * targets, dimensions, chain counts and draw counts (ESS jobs in FP32 and
+ * DRMH jobs).  One round is one replay of a captured hipGraph whose kernels
+ * serve every job at once:
+ *   - a grouped ellipse GEMM: the next `window` directions nu = L z of every
+ *     ESS chain, all jobs' column blocks in one launch per tile shape;
+ *   - one persistent FSM kernel: its wavefronts take work items from a
+ *     device queue, longest first -- one ESS chain for `window` draws, or 64
+ *     DRMH chains (one per lane) for `dr_chunk` draws -- and run the chains'
+ *     FSM steps (Sec. 3.2, Alg. "Vectorized FSM MCMC algorithm") without
+ *     waiting for any other chain or job.
+ * Chains of a job never synchronise with other jobs, and a job's draws are
+ * bit-identical to running it alone with fsmmc_step_fsm.  While a job
+ * belongs to a batch, the per-job stepping calls and fsmmc_job_free return
+ * EBUSY. */
+typedef struct fsmmc_batch fsmmc_batch;
+
+typedef struct {
+    int32_t autotune;        /* 1: choose window, dr_chunk and gemm_cols from measured
+                                rounds (the tuning rounds do real work)              */
+    int32_t window;          /* ESS draws per chain per round (0 = 16), capped by the
+                                direction buffer each job was created with           */
+    int32_t dr_chunk;        /* DRMH draws per chain per round (0 = 16)              */
+    int32_t gemm_cols;       /* ellipse GEMM columns per block, 64 or 128 (0 = 64;
+                                128 applies to jobs with dim <= 512)                 */
+    int32_t rounds_per_sync; /* graph replays between progress reads (0 = 4)         */
+    int32_t reserved[3];
+} fsmmc_batch_tune;
+
+typedef struct {
+    int64_t rounds;      /* graph replays                                           */
+    int64_t captures;    /* graphs captured (start, after jobs finish, tuning)      */
+    int64_t draws;       /* draws produced by the batch, summed over jobs and chains */
+    int32_t window;      /* configuration in use                                     */
+    int32_t dr_chunk;
+    int32_t gemm_cols;
+    int32_t live_jobs;   /* jobs with a chain short of its n_draws                  */
+    double gpu_ms;       /* device time of all replays (HIP events on the stream)   */
+    double tune_ms;      /* part of gpu_ms spent in autotuning rounds               */
+    int32_t tune_trials; /* configurations the autotuner measured                   */
+    int32_t fsm_blocks;  /* workgroups of the persistent FSM kernel                 */
+} fsmmc_batch_counters;
+
+/* Group n_jobs jobs of context ctx into a batch stepped on `stream`
+ * (hipStream_t; NULL = a stream the batch creates).  The jobs must be ESS
+ * (FP32) or DRMH jobs not already in a batch; their queued initialisation is
+ * waited for.  Errors: EINVAL (null or repeated job, other context),
+ * ENOTSUP (NUTS or FP64 job), EBUSY (job in another batch), EDEVICE. */
+fsmmc_status fsmmc_batch_create(fsmmc_ctx* ctx, fsmmc_job* const* jobs, int32_t n_jobs,
+                                void* stream, const fsmmc_batch_tune* tune,
+                                fsmmc_batch** out);
+
+/* Replay rounds until every chain of every job has its n_draws draws, or
+ * max_rounds rounds have run (max_rounds <= 0: no limit).  Synchronises the
+ * batch's stream.  all_done (may be NULL) receives 1 when every job is
+ * complete. */
+fsmmc_status fsmmc_batch_run(fsmmc_batch* batch, int64_t max_rounds, int32_t* all_done);
+
+/* Counters and the configuration in use. */
+fsmmc_status fsmmc_batch_stats(fsmmc_batch* batch, fsmmc_batch_counters* out);
+
+/* Release the batch (not its jobs, which become free-standing again). */
+fsmmc_status fsmmc_batch_free(fsmmc_batch* batch);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char* fsmmc_last_error(void);
 

@@ -1,0 +1,367 @@
+// ess_device.h -- elliptical slice sampling (Murray, Adams, MacKay 2010)
+// building blocks shared by the single-job kernels (ess.hip) and the grouped
+// multi-job kernels (batch.hip).  Sec. 3.1: states INIT, SHRINK, DONE;
+// Appendix, Alg. "Transition kernel for elliptical slice sampler".
+//
+// Every kernel that advances an ESS chain calls these functions in the same
+// order, so a chain's draws are the same bits whichever kernel runs it.
+#pragma once
+#include "fsmmc_device.h"
+#include "fsmmc_internal.h"
+
+namespace fsmmc {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// Ellipse-direction product nu = L z for the columns (chain, w) of a window.
+template <typename T>
+struct NuK {
+    int m, n, D, Dp, W;
+    uint64_t seed;
+    uint32_t role;
+    int draw_fixed;     // >= 0: every column uses this draw; < 0: draw = t[chain] + w
+    const uint32_t* t;  // chain draw counters
+    const T* L;         // Dp x Dp lower factor, zero padded
+    T* out;             // column (chain, w) -> out[(chain * W + w) * Dp + row]
+};
+
+template <typename T>
+struct EssK {
+    int m, n, D, Dp, W, target;
+    uint64_t seed;
+    T inv2v;
+    const T* y;
+    const T* nu;
+    int32_t* k;
+    uint32_t* t;
+    int32_t* evals;
+    int64_t* budget;
+    T *theta, *tmin, *tmax, *logy, *lx, *x, *out;
+    int32_t* counts;
+    unsigned long long* ctr;
+    int32_t* maxN;
+    T* sink;
+};
+
+// ------------------------------------------------------------ ellipse GEMM
+// One block of 8 waves computes NC = 32 CT columns (col0 ..) over all Dp rows.
+// Wave w owns RT row tiles of 32 rows in "snake" order (w, 15-w, 16+w, 31-w,
+// ...) so the triangular work is balanced across waves.  Per K chunk of 32:
+// the block draws its 32 x NC normals into LDS (one Philox block per thread
+// and 64 columns), then every wave multiplies its L rows (read as float4
+// along k from L2) by them.  The MFMA (32x32x2, FP32 accumulation) computes
+// nu^T = z^T L^T so each output register row is 32 consecutive nu entries of
+// one column (128-byte coalesced stores).  A block whose columns are all past
+// their chain's last draw exits at once.
+template <int RT, int CT = 2>
+__device__ __forceinline__ void nu_gemm_block(const NuK<float>& a, int col0)
+{
+    static_assert(CT == 2 || CT == 4, "64 or 128 columns per block");
+    constexpr int NC = 32 * CT, ZC = CT / 2;
+    __shared__ float Zs[32][NC];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, l32 = lane & 31;
+    const int ncols = a.m * a.W;
+
+    const int zc = tid & 63, zb = tid >> 6;
+    bool zvalid[ZC];
+    int zchain[ZC];
+    uint32_t zdraw[ZC];
+    int any = 0;
+#pragma unroll
+    for (int cc = 0; cc < ZC; ++cc) {
+        const int gcol = col0 + zc + 64 * cc;
+        zvalid[cc] = gcol < ncols;
+        zchain[cc] = 0;
+        zdraw[cc] = 0;
+        if (zvalid[cc]) {
+            zchain[cc] = gcol / a.W;
+            const int zw = gcol - zchain[cc] * a.W;
+            zdraw[cc] = a.draw_fixed >= 0 ? (uint32_t)a.draw_fixed : a.t[zchain[cc]] + (uint32_t)zw;
+            zvalid[cc] = a.draw_fixed >= 0 || zdraw[cc] < (uint32_t)a.n;
+        }
+        any |= zvalid[cc] ? 1 : 0;
+    }
+    if (!__syncthreads_or(any)) return;
+
+    const int ntiles = a.Dp >> 5;
+    int tiles[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+        const int idx = (r & 1) ? r * 8 + 7 - wave : r * 8 + wave;
+        tiles[r] = idx < ntiles ? idx : -1;
+    }
+    floatx16 acc[RT][CT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[r][c][q] = 0.0f;
+
+    for (int kc = 0; kc < a.Dp; kc += 32) {
+        const int kb = kc + 4 * zb;
+#pragma unroll
+        for (int cc = 0; cc < ZC; ++cc) {
+            float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (zvalid[cc] && kb < a.D) {
+                normals4<float>(a.seed, (uint32_t)zchain[cc], zdraw[cc], a.role, 0, (uint32_t)(kb >> 2), z);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (kb + i >= a.D) z[i] = 0.0f;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Zs[4 * zb + i][zc + 64 * cc] = z[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            const int ti = tiles[r];
+            if (ti < 0 || 32 * ti + 31 < kc) continue;
+            const float4* Lr =
+                reinterpret_cast<const float4*>(a.L + (size_t)(32 * ti + l32) * a.Dp + kc + 16 * h);
+            float lr[16];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float4 q4 = Lr[v];
+                lr[4 * v + 0] = q4.x;
+                lr[4 * v + 1] = q4.y;
+                lr[4 * v + 2] = q4.z;
+                lr[4 * v + 3] = q4.w;
+            }
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    const float av = Zs[16 * h + kk][c * 32 + l32];
+                    acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, lr[kk], acc[r][c], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+        const int ti = tiles[r];
+        if (ti < 0) continue;
+        const int row = 32 * ti + l32;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int col = c * 32 + 8 * (q >> 2) + 4 * h + (q & 3);
+                const int g = col0 + col;
+                if (g < ncols) {
+                    const int ch = g / a.W, w = g - ch * a.W;
+                    a.out[((size_t)ch * a.W + w) * a.Dp + row] = acc[r][c][q];
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ ESS blocks
+template <typename T>
+__device__ __forceinline__ T ess_term(T f, T yv, int target, T inv2v)
+{
+    if (target == FSMMC_GP_GAUSS) {
+        const T r = yv - f;
+        return -(r * r) * inv2v;
+    }
+    return yv * f - M<T>::softplus(f);
+}
+
+// x' = x cos(theta) + nu sin(theta) and log L(x'), summed in a fixed order
+// (lane-local over e, then a wave butterfly); the result is wave-uniform.
+template <typename T, int EPL>
+__device__ __forceinline__ T ess_propose_eval(const T (&x)[EPL], const T (&nu)[EPL], T (&xp)[EPL],
+                                              const T (&yv)[EPL], T theta, int lane, int D, int target,
+                                              T inv2v)
+{
+    T s, c;
+    M<T>::sincos_(theta, &s, &c);
+    T acc = T(0);
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+        const T f = M<T>::fma_(x[e], c, nu[e] * s);
+        xp[e] = f;
+        const T term = ess_term(f, yv[e], target, inv2v);
+        acc += (e * 64 + lane < D) ? term : T(0);
+    }
+    return wave_sum(acc);
+}
+
+// INIT: threshold log y = log L(x) + log u and the initial bracket.
+template <typename T>
+__device__ __forceinline__ void ess_begin(uint64_t seed, uint32_t chain, uint32_t draw, T lx, T& logy,
+                                          T& theta, T& tmin, T& tmax)
+{
+    logy = lx + M<T>::log_(uniform<T>(seed, chain, draw, ROLE_THRESH, 0));
+    theta = Pi<T>::two_pi * uniform<T>(seed, chain, draw, ROLE_ANGLE, 0);
+    tmin = theta - Pi<T>::two_pi;
+    tmax = theta;
+}
+
+// SHRINK: move the bracket end on theta's side to theta, draw a new angle.
+template <typename T>
+__device__ __forceinline__ void ess_shrink(uint64_t seed, uint32_t chain, uint32_t draw, int evals,
+                                           T& theta, T& tmin, T& tmax)
+{
+    if (theta < T(0))
+        tmin = theta;
+    else
+        tmax = theta;
+    theta = tmin + (tmax - tmin) * uniform<T>(seed, chain, draw, ROLE_ANGLE, (uint32_t)evals);
+}
+
+template <typename T, int EPL>
+__device__ __forceinline__ void ess_emit(const EssK<T>& a, int j, uint32_t t, const T (&x)[EPL], int evals,
+                                         int lane)
+{
+    T* o = a.out + ((size_t)j * a.n + t) * a.D;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+        const int d = e * 64 + lane;
+        if (d < a.D) o[d] = x[e];
+    }
+    if (lane == 0) a.counts[(size_t)j * a.n + t] = evals;
+}
+
+// One wave runs chain j through FSM steps until it has used the ellipse
+// window [t0, t0 + W), reached n draws, or spent its step budget.  Returns
+// the number of draws it emitted.  Counters: [0] steps, [2] guard trips,
+// [4] chains still short of n, [3] of those, chains with budget left.
+template <typename T, int EPL>
+__device__ __forceinline__ uint32_t ess_window(const EssK<T>& a, int j, int lane)
+{
+    uint32_t t = a.t[j];
+    if (t >= (uint32_t)a.n) return 0;
+    const uint32_t t0 = t;
+    const uint32_t wend = min(t0 + (uint32_t)a.W, (uint32_t)a.n);
+    int k = a.k[j], evals = a.evals[j];
+    T theta = a.theta[j], tmin = a.tmin[j], tmax = a.tmax[j], logy = a.logy[j], lx = a.lx[j];
+    int64_t budget = a.budget[j];
+
+    T x[EPL], nu[EPL], xp[EPL], yv[EPL];
+    const T* xj = a.x + (size_t)j * a.Dp;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+        x[e] = xj[e * 64 + lane];
+        yv[e] = a.y[e * 64 + lane];
+    }
+    unsigned long long steps = 0;
+    int guards = 0;
+    bool have_nu = false;
+    while (t < wend && budget > 0) {
+        if (!have_nu) {
+            const T* nj = a.nu + ((size_t)j * a.W + (t - t0)) * a.Dp;
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) nu[e] = nj[e * 64 + lane];
+            have_nu = true;
+        }
+        if (k == 1) {
+            ess_begin<T>(a.seed, (uint32_t)j, t, lx, logy, theta, tmin, tmax);
+            evals = 0;
+        } else {
+            ess_shrink<T>(a.seed, (uint32_t)j, t, evals, theta, tmin, tmax);
+        }
+        const T lp = ess_propose_eval<T, EPL>(x, nu, xp, yv, theta, lane, a.D, a.target, a.inv2v);
+        ++evals;
+        ++steps;
+        --budget;
+        const bool accept = lp > logy;
+        if (accept || evals >= kEssMaxEvals) {
+            if (accept) {
+#pragma unroll
+                for (int e = 0; e < EPL; ++e) x[e] = xp[e];
+                lx = lp;
+            } else {
+                ++guards;
+            }
+            ess_emit<T, EPL>(a, j, t, x, evals, lane);
+            ++t;
+            k = 1;
+            have_nu = false;
+        } else {
+            k = 2;
+        }
+    }
+    T* xo = a.x + (size_t)j * a.Dp;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) xo[e * 64 + lane] = x[e];
+    if (lane == 0) {
+        a.t[j] = t;
+        a.k[j] = k;
+        a.evals[j] = evals;
+        a.theta[j] = theta;
+        a.tmin[j] = tmin;
+        a.tmax[j] = tmax;
+        a.logy[j] = logy;
+        a.lx[j] = lx;
+        a.budget[j] = budget;
+        atomicAdd(&a.ctr[0], steps);
+        if (guards) atomicAdd(&a.ctr[2], (unsigned long long)guards);
+        if (t < (uint32_t)a.n) {
+            atomicAdd(&a.ctr[4], 1ull);
+            if (budget > 0) atomicAdd(&a.ctr[3], 1ull);
+        }
+    }
+    return t - t0;
+}
+
+// ------------------------------------------------------------ host views
+template <typename T>
+inline EssK<T> ess_view(const JobDev& j)
+{
+    EssK<T> a;
+    a.m = j.m;
+    a.n = j.n;
+    a.D = j.D;
+    a.Dp = j.Dp;
+    a.W = j.W;
+    a.target = j.target;
+    a.seed = j.seed;
+    a.inv2v = (j.target == FSMMC_GP_GAUSS) ? (T)(1.0 / (2.0 * j.noise_sd * j.noise_sd)) : T(0);
+    a.y = (const T*)j.y;
+    a.nu = (const T*)j.nu;
+    a.k = j.k;
+    a.t = j.t;
+    a.evals = j.evals;
+    a.budget = j.budget;
+    a.theta = (T*)j.theta;
+    a.tmin = (T*)j.tmin;
+    a.tmax = (T*)j.tmax;
+    a.logy = (T*)j.logy;
+    a.lx = (T*)j.lx;
+    a.x = (T*)j.x;
+    a.out = (T*)j.out;
+    a.counts = j.counts;
+    a.ctr = j.ctr;
+    a.maxN = j.maxN;
+    a.sink = (T*)j.sink;
+    return a;
+}
+
+// Window product of the job's next W draws per chain.
+template <typename T>
+inline NuK<T> ess_window_view(const JobDev& j)
+{
+    NuK<T> a;
+    a.m = j.m;
+    a.n = j.n;
+    a.D = j.D;
+    a.Dp = j.Dp;
+    a.W = j.W;
+    a.seed = j.seed;
+    a.role = ROLE_NU;
+    a.draw_fixed = -1;
+    a.t = j.t;
+    a.L = (const T*)j.L;
+    a.out = (T*)j.nu;
+    return a;
+}
+
+// Row tiles of 32 per GEMM wave (8 waves) for the job's padded dimension.
+inline int ess_gemm_rt(int Dp) { return (Dp / 32 + 7) / 8; }
+
+}  // namespace fsmmc

@@ -11,30 +11,13 @@
 #include <string>
 #include <vector>
 
-#include "fsmmc_internal.h"
+#include "fsmmc_host.h"
 
 using namespace fsmmc;
 
+namespace fsmmc {
 namespace {
 thread_local std::string g_err;
-
-fsmmc_status fail(fsmmc_status s, const std::string& msg)
-{
-    g_err = msg;
-    return s;
-}
-
-fsmmc_status hip_fail(hipError_t e, const char* what)
-{
-    g_err = std::string(what) + ": " + hipGetErrorString(e);
-    return FSMMC_EDEVICE;
-}
-
-#define HIP_TRY(expr)                                          \
-    do {                                                       \
-        hipError_t e__ = (expr);                               \
-        if (e__ != hipSuccess) return hip_fail(e__, #expr);    \
-    } while (0)
 
 __global__ void fill_i64_kernel(int64_t* p, int64_t v, int n)
 {
@@ -49,75 +32,33 @@ __global__ void fill_i32_kernel(int32_t* p, int32_t v, int n)
 }
 }  // namespace
 
-struct fsmmc_ctx {
-    int device = 0;
-    size_t budget = 0;
-    std::atomic<size_t> used{0};
-    std::atomic<int> jobs{0};
-};
-
-struct TimedLaunch {
-    hipEvent_t a, b;
-    int cls;
-};
-
-struct fsmmc_job {
-    fsmmc_ctx* ctx = nullptr;
-    hipStream_t stream = nullptr;
-    JobDev d;
-    std::vector<void*> allocs;
-    size_t bytes = 0;
-    unsigned long long* h_ctr = nullptr;  // pinned: [0..7] mirror of d.ctr, [8..15] scratch reads
-    int launches = 0;
-    uint32_t step = 0;  // NUTS runtime step counter (keys the per-step counters)
-    // optional per-launch device timing
-    bool timing = false;
-    std::vector<hipEvent_t> pool;
-    std::vector<TimedLaunch> pending;
-    double kms[4] = {0, 0, 0, 0};
-    int klaunch[4] = {0, 0, 0, 0};
-};
-
-// Kernel classes of fsmmc_stats.kernel_ms.
-enum { KC_G = 0, KC_FSM = 1, KC_SYNC = 2, KC_PAD = 3 };
-
-static hipEvent_t ev_get(fsmmc_job* j)
+fsmmc_status fail(fsmmc_status s, const std::string& msg)
 {
-    hipEvent_t e = nullptr;
-    if (!j->pool.empty()) {
-        e = j->pool.back();
-        j->pool.pop_back();
-    } else if (hipEventCreate(&e) != hipSuccess) {
-        e = nullptr;
-    }
-    return e;
+    g_err = msg;
+    return s;
 }
 
-// Queue one launcher call; with timing on, bracket it with events.
-template <typename F>
-static hipError_t launch(fsmmc_job* j, int cls, F&& fn)
+fsmmc_status hip_fail(hipError_t e, const char* what)
 {
-    hipEvent_t a = nullptr, b = nullptr;
-    if (j->timing) {
-        a = ev_get(j);
-        if (a) (void)hipEventRecord(a, j->stream);
-    }
-    hipError_t e = fn();
-    j->launches++;
-    if (j->timing && a) {
-        b = ev_get(j);
-        if (b) {
-            (void)hipEventRecord(b, j->stream);
-            j->pending.push_back({a, b, cls});
-        } else {
-            j->pool.push_back(a);
-        }
-    }
-    return e;
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return FSMMC_EDEVICE;
 }
 
-// After the stream has drained: fold the recorded intervals into the totals.
-static void harvest(fsmmc_job* j)
+hipError_t fill_i64(int64_t* p, int64_t v, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t fill_i32(int32_t* p, int32_t v, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+void harvest(fsmmc_job* j)
 {
     for (const TimedLaunch& t : j->pending) {
         float ms = 0.0f;
@@ -130,6 +71,8 @@ static void harvest(fsmmc_job* j)
     }
     j->pending.clear();
 }
+
+}  // namespace fsmmc
 
 static fsmmc_status job_alloc(fsmmc_job* j, size_t bytes, void** p)
 {
@@ -357,6 +300,7 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
         }
         d.W = std::max(1, std::min(W, d.n));
         while ((int64_t)d.W * d.m > (int64_t)1 << 30 && d.W > 1) d.W /= 2;
+        d.Wcap = d.W;
         ALLOC(d.nu, m * (size_t)d.W * Dp * es);
         fsmmc_status s2 = stage_lower(job, target->chol_L, d.D, d.Dp, es, d.L);
         if (s2 != FSMMC_OK) {
@@ -492,6 +436,7 @@ static fsmmc_status nuts_run(fsmmc_job* job, int mode, int64_t max_steps, uint32
 fsmmc_status fsmmc_step_fsm(fsmmc_job* job, int64_t max_steps, int32_t* all_done)
 {
     if (!job) return fail(FSMMC_EINVAL, "job is NULL");
+    if (job->batch) return fail(FSMMC_EBUSY, "job is stepped by a batch or server");
     JobDev& d = job->d;
     HIP_TRY(hipSetDevice(job->ctx->device));
     if (d.kind == FSMMC_NUTS) return nuts_run(job, 0, max_steps, (uint32_t)d.n, all_done);
@@ -530,6 +475,7 @@ fsmmc_status fsmmc_step_fsm(fsmmc_job* job, int64_t max_steps, int32_t* all_done
 fsmmc_status fsmmc_step_synchronized(fsmmc_job* job, int32_t n_draws, int32_t mode, int32_t* all_done)
 {
     if (!job) return fail(FSMMC_EINVAL, "job is NULL");
+    if (job->batch) return fail(FSMMC_EBUSY, "job is stepped by a batch or server");
     if (mode != FSMMC_SYNC_VMAP && mode != FSMMC_SYNC_COMPACT) return fail(FSMMC_EINVAL, "bad mode");
     JobDev& d = job->d;
     HIP_TRY(hipSetDevice(job->ctx->device));
@@ -612,6 +558,7 @@ fsmmc_status fsmmc_collect_counts(fsmmc_job* job, int32_t* dst)
 fsmmc_status fsmmc_eval_potential(fsmmc_job* job, int32_t n_points, const void* theta, void* grad, void* U)
 {
     if (!job || !theta || !U) return fail(FSMMC_EINVAL, "job, theta or U is NULL");
+    if (job->batch) return fail(FSMMC_EBUSY, "job is stepped by a batch or server");
     JobDev& d = job->d;
     if (d.kind != FSMMC_NUTS) return fail(FSMMC_ENOTSUP, "only NUTS jobs evaluate a potential");
     if (n_points < 1 || n_points > d.m) return fail(FSMMC_EINVAL, "n_points must be in [1, n_chains]");
@@ -682,6 +629,7 @@ fsmmc_status fsmmc_job_sync(fsmmc_job* job)
 fsmmc_status fsmmc_job_free(fsmmc_job* job)
 {
     if (!job) return fail(FSMMC_EINVAL, "job is NULL");
+    if (job->batch) return fail(FSMMC_EBUSY, "job is stepped by a batch or server");
     job_release(job);
     return FSMMC_OK;
 }

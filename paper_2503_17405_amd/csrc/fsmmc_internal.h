@@ -47,8 +47,9 @@ struct JobDev {
     void* tmin = nullptr;
     void* tmax = nullptr;
     void* logy = nullptr;
-    void* nu = nullptr;  // m x W x Dp ellipse directions of the current window
-    int W = 0;
+    void* nu = nullptr;  // m x Wcap x Dp ellipse directions of the current window
+    int W = 0;           // draws per window (<= Wcap)
+    int Wcap = 0;        // draws the direction buffer holds per chain
 
     // NUTS
     int32_t* jd = nullptr;     // tree depth of the subtree being built

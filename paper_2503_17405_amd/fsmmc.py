@@ -27,6 +27,7 @@ EXPORTS = [
     "fsmmc_step_fsm", "fsmmc_step_synchronized", "fsmmc_collect_samples", "fsmmc_collect_counts",
     "fsmmc_chain_progress", "fsmmc_job_stats", "fsmmc_job_sync", "fsmmc_job_free",
     "fsmmc_last_error", "fsmmc_version", "fsmmc_eval_potential",
+    "fsmmc_batch_create", "fsmmc_batch_run", "fsmmc_batch_stats", "fsmmc_batch_free",
 ]
 
 
@@ -58,6 +59,21 @@ class Stats(C.Structure):
         return d
 
 
+class BatchTune(C.Structure):
+    _fields_ = [("autotune", C.c_int32), ("window", C.c_int32), ("dr_chunk", C.c_int32),
+                ("gemm_cols", C.c_int32), ("rounds_per_sync", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
+class BatchCounters(C.Structure):
+    _fields_ = [("rounds", C.c_int64), ("captures", C.c_int64), ("draws", C.c_int64),
+                ("window", C.c_int32), ("dr_chunk", C.c_int32), ("gemm_cols", C.c_int32),
+                ("live_jobs", C.c_int32), ("gpu_ms", C.c_double), ("tune_ms", C.c_double),
+                ("tune_trials", C.c_int32), ("fsm_blocks", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class FsmmcError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("fsmmc error %d: %s" % (status, msg))
@@ -85,6 +101,10 @@ def _load():
         "fsmmc_job_stats": ([p, p], C.c_int),
         "fsmmc_job_sync": ([p], C.c_int),
         "fsmmc_job_free": ([p], C.c_int),
+        "fsmmc_batch_create": ([p, pp, i32, p, p, pp], C.c_int),
+        "fsmmc_batch_run": ([p, i64, p], C.c_int),
+        "fsmmc_batch_stats": ([p, p], C.c_int),
+        "fsmmc_batch_free": ([p], C.c_int),
         "fsmmc_last_error": ([], C.c_char_p),
         "fsmmc_version": ([], C.c_char_p),
     }
@@ -186,6 +206,31 @@ def fsmmc_job_sync(job):
 
 def fsmmc_job_free(job):
     _check(lib.fsmmc_job_free(job))
+
+
+def fsmmc_batch_create(ctx, jobs, stream=None, tune=None):
+    arr = (C.c_void_p * len(jobs))(*[j.value for j in jobs])
+    out = C.c_void_p()
+    st = None if stream is None else C.c_void_p(stream.cuda_stream)
+    _check(lib.fsmmc_batch_create(ctx, C.cast(arr, C.POINTER(C.c_void_p)), len(jobs), st,
+                                  None if tune is None else C.byref(tune), C.byref(out)))
+    return out
+
+
+def fsmmc_batch_run(batch, max_rounds=0):
+    done = C.c_int32()
+    _check(lib.fsmmc_batch_run(batch, max_rounds, C.byref(done)))
+    return bool(done.value)
+
+
+def fsmmc_batch_stats(batch):
+    s = BatchCounters()
+    _check(lib.fsmmc_batch_stats(batch, C.byref(s)))
+    return s.as_dict()
+
+
+def fsmmc_batch_free(batch):
+    _check(lib.fsmmc_batch_free(batch))
 
 
 # ------------------------------------------------------------- convenience
@@ -304,4 +349,25 @@ class Job:
     def free(self):
         if self.handle is not None:
             fsmmc_job_free(self.handle)
+            self.handle = None
+
+
+class Batch:
+    """Several jobs stepped together (one graph replay per round)."""
+
+    def __init__(self, ctx, jobs, stream=None, autotune=False, window=0, dr_chunk=0, gemm_cols=0,
+                 rounds_per_sync=0):
+        self.jobs = list(jobs)
+        tune = BatchTune(1 if autotune else 0, window, dr_chunk, gemm_cols, rounds_per_sync)
+        self.handle = fsmmc_batch_create(ctx.handle, [j.handle for j in self.jobs], stream, tune)
+
+    def run(self, max_rounds=0):
+        return fsmmc_batch_run(self.handle, max_rounds)
+
+    def stats(self):
+        return fsmmc_batch_stats(self.handle)
+
+    def free(self):
+        if self.handle is not None:
+            fsmmc_batch_free(self.handle)
             self.handle = None
