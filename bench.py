@@ -15,6 +15,13 @@ Reported beside it, on the same box and run:
   * NUTS on Bayesian logistic regression (N = 10000, D = 100, step 0.05,
     depth 10, Laplace starts), 8192 chains x 1000 draws, FSM vs synchronized;
   * R(m) of each job estimated from its own loop counts;
+  * batching: 32 GP-logistic ESS targets of uneven dim / chains / draws plus a
+    65536-chain D=10 funnel under 3-stage delayed rejection, in one batch
+    (one graph replay per round, autotuned), against the same jobs run one
+    after another; bit-identical outputs checked;
+  * serving: a Poisson stream of ESS-GP and NUTS jobs of random sizes through
+    the continuous-batching server, against one-job-at-a-time on the same
+    stream: p50/p99 latency and draws/s, bit-identical outputs checked;
   * the live roofline figure of the dominant kernel (HIP events);
   * the FP64 CPU oracle timed on a bounded sample of the ESS workload.
 """
@@ -157,6 +164,177 @@ def bench_nuts(F, ctx, args):
     return res
 
 
+def _ess_job_data(F, D, ds, cache):
+    import torch
+
+    from paper_2503_17405_amd import inputs
+    if (D, ds) not in cache:
+        w = inputs.gp_logistic(dim=D, lengthscale=0.05, jitter=1e-5, seed=ds)
+        cache[(D, ds)] = (torch.tensor(w["L"], dtype=torch.float32, device="cuda"),
+                          torch.tensor(w["y"], dtype=torch.float32, device="cuda"))
+    L, y = cache[(D, ds)]
+    return F.gp_target(L, y)
+
+
+def bench_batch(F, ctx, args):
+    """Uneven batch: 32 ESS GP-logistic targets + the 65536-chain funnel."""
+    import torch
+
+    from paper_2503_17405_amd import inputs
+    spec = inputs.ess_uneven_targets()
+    cache = {}
+    jobs_spec = [("ess", s["dim"], s["n_chains"], s["n_draws"], s["data_seed"], s["chain_seed"]) for s in spec]
+    jobs_spec.append(("dr", 10, args.funnel_chains, 1000, 0, 4002))
+    outs = [torch.empty((m, n, D), dtype=torch.float32, device="cuda") for _, D, m, n, _, _ in jobs_spec]
+    draws = sum(m * n for _, _, m, n, _, _ in jobs_spec)
+
+    def make(k):
+        kind, D, m, n, ds, cs = jobs_spec[k]
+        if kind == "ess":
+            return F.Job(ctx, _ess_job_data(F, D, ds, cache), F.ess_sampler(), m, n, cs, out=outs[k])
+        return F.Job(ctx, F.funnel_target(D), F.dr_sampler((1.0, 0.3, 0.1)), m, n, cs, out=outs[k])
+
+    log("C4 batch (%d jobs, %d draws)" % (len(jobs_spec), draws))
+    jobs = [make(k) for k in range(len(jobs_spec))]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = F.Batch(ctx, jobs, autotune=True)
+    b.run(0)
+    t_batch = time.perf_counter() - t0
+    st = b.stats()
+    b.free()
+    for j in jobs:
+        j.free()
+    sums = [checksum(o) for o in outs]
+    log("C4 one job at a time")
+    t_alone = 0.0
+    for k in range(len(jobs_spec)):
+        j = make(k)
+        j.sync()
+        t1 = time.perf_counter()
+        while not j.step_fsm(0):
+            pass
+        t_alone += time.perf_counter() - t1
+        j.free()
+    same = all(checksum(o) == s for o, s in zip(outs, sums))
+    del outs
+    torch.cuda.empty_cache()
+    return dict(workload="32 GP-logistic ESS targets (D~U{64..1024}, m~U{256..2048}, n~U{200..2000}) + "
+                         "3-stage DR on the D=10 funnel (%d chains x 1000 draws), FP32" % args.funnel_chains,
+                jobs=len(jobs_spec), draws=draws, batch_s=t_batch, alone_s=t_alone,
+                draws_per_s_batch=draws / t_batch, draws_per_s_alone=draws / t_alone,
+                speedup=t_alone / t_batch, bit_exact_vs_alone=bool(same), rounds=st["rounds"],
+                captures=st["captures"], gpu_ms=st["gpu_ms"], tuned=dict(window=st["window"],
+                dr_chunk=st["dr_chunk"], gemm_cols=st["gemm_cols"], trials=st["tune_trials"],
+                tune_ms=st["tune_ms"]))
+
+
+def serve_stream(n_jobs, seed):
+    """Job list of the serving stream: Poisson arrivals at 50 jobs/s, half
+    ESS GP-logistic (D~U{64..1024}), half NUTS logistic regression
+    (D~U{10..100}, N~U{1000..10000}), m~U{16..1024}, n~U{200..2000}."""
+    import numpy as np
+    g = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    for k in range(n_jobs):
+        t += g.exponential(0.02)
+        m = int(g.integers(16, 1025))
+        n = int(g.integers(200, 2001))
+        if g.uniform() < 0.5:
+            out.append(dict(kind="ess", t=t, m=m, n=n, D=int(g.integers(64, 1025)),
+                            data_seed=int(g.integers(1 << 31)), seed=int(g.integers(1 << 62))))
+        else:
+            out.append(dict(kind="nuts", t=t, m=m, n=n, D=int(g.integers(10, 101)),
+                            N=int(g.integers(1000, 10001)), data_seed=int(g.integers(1 << 31)),
+                            seed=int(g.integers(1 << 62))))
+    return out
+
+
+def bench_serve(F, args):
+    import numpy as np
+    import torch
+
+    from paper_2503_17405_amd import inputs
+    stream = serve_stream(args.serve_jobs, 5001)
+    log("C5 stream: %d jobs, preparing inputs" % len(stream))
+    t0 = time.perf_counter()
+    cache, data = {}, []
+    for js in stream:
+        if js["kind"] == "ess":
+            tgt = _ess_job_data(F, js["D"], js["data_seed"], cache)
+            data.append((tgt, F.ess_sampler(), None))
+        else:
+            d = inputs.logreg(n_data=js["N"], dim=js["D"], seed=js["data_seed"])
+            lap = inputs.logreg_laplace(d["X"], d["y"], js["m"], seed=js["data_seed"] + 1)
+            lam = float(np.linalg.eigvalsh(lap["hessian"])[-1])
+            eps = min(0.05, 1.0 / np.sqrt(lam))
+            X = torch.tensor(d["X"], dtype=torch.float32, device="cuda")
+            y = torch.tensor(d["y"], dtype=torch.float32, device="cuda")
+            x0 = torch.tensor(lap["x0"], dtype=torch.float32, device="cuda")
+            data.append((F.logreg_target(X, y), F.nuts_sampler(eps, 10), x0))
+            js["eps"] = eps
+    outs = [torch.empty((js["m"], js["n"], js["D"]), dtype=torch.float32, device="cuda") for js in stream]
+    torch.cuda.synchronize()
+    prep_s = time.perf_counter() - t0
+    draws = sum(js["m"] * js["n"] for js in stream)
+
+    def latencies(lat):
+        lat = np.sort(np.asarray(lat))
+        return dict(p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                    mean_s=float(lat.mean()), max_s=float(lat.max()))
+
+    log("C5 server")
+    ctx = F.Context(0, hbm_budget_bytes=args.serve_budget_gib << 30)
+    srv = F.Server(ctx)
+    ids = []
+    start = F.clock()
+    for k, js in enumerate(stream):
+        while F.clock() - start < js["t"]:
+            time.sleep(min(0.002, max(0.0, js["t"] - (F.clock() - start))))
+        tgt, smp, x0 = data[k]
+        ids.append(srv.submit(tgt, smp, js["m"], js["n"], js["seed"], outs[k], x0=x0))
+    srv.wait(-1.0)
+    recs = {r["job_id"]: r for r in srv.poll(len(stream) + 8)}
+    sst = srv.stats()
+    srv.close()
+    ctx.close()
+    ok = all(recs[i]["status"] == F.OK for i in ids)
+    lat_srv = [recs[i]["t_done"] - recs[i]["t_submit"] for i in ids]
+    span_srv = max(recs[i]["t_done"] for i in ids) - start
+    sums = [checksum(o) for o in outs]
+
+    log("C5 one job at a time")
+    ctx = F.Context(0)
+    start = F.clock()
+    lat_one, t_done = [], 0.0
+    for k, js in enumerate(stream):
+        now = F.clock() - start
+        if now < js["t"]:
+            time.sleep(js["t"] - now)
+        tgt, smp, x0 = data[k]
+        j = F.Job(ctx, tgt, smp, js["m"], js["n"], js["seed"], x0=x0, out=outs[k], window=16)
+        while not j.step_fsm(0):
+            pass
+        j.free()
+        t_done = F.clock() - start
+        lat_one.append(t_done - js["t"])
+    ctx.close()
+    same = all(checksum(o) == s for o, s in zip(outs, sums))
+    del outs
+    torch.cuda.empty_cache()
+    return dict(workload="%d jobs, Poisson arrivals at 50 jobs/s; ESS GP-logistic D~U{64..1024} or NUTS "
+                         "logistic regression D~U{10..100}, N~U{1000..10000}; m~U{16..1024}, "
+                         "n~U{200..2000}; FP32" % len(stream),
+                jobs=len(stream), draws=draws, host_prep_s=prep_s, all_ok=bool(ok),
+                bit_exact_vs_alone=bool(same), hbm_budget_gib=args.serve_budget_gib,
+                server=dict(draws_per_s=draws / span_srv, span_s=span_srv, **latencies(lat_srv),
+                            rounds=sst["rounds"], gpu_ms=sst["gpu_ms"], peak_live_jobs=sst["peak_live_jobs"],
+                            peak_state_gib=sst["peak_bytes"] / 2 ** 30),
+                one_at_a_time=dict(draws_per_s=draws / t_done, span_s=t_done, **latencies(lat_one)),
+                throughput_gain=(draws / span_srv) / (draws / t_done))
+
+
 def cpu_baseline(w, seed, chains, draws, threads):
     from oracle import oracle as O
     tg = O.gp_target(w["y"])
@@ -186,6 +364,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sync", action="store_true")
     ap.add_argument("--cpu-draws", type=int, default=2000)
+    ap.add_argument("--cpu-chains-per-thread", type=int, default=16)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--funnel-chains", type=int, default=65536)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=120)
+    ap.add_argument("--serve-budget-gib", type=int, default=64)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -204,12 +388,24 @@ def main():
     if not args.no_nuts:
         nuts = bench_nuts(F, ctx, args)
         log("NUTS: FSM %.3g draws/s" % nuts["draws_per_s"])
+    batch = None
+    if not args.no_batch:
+        batch = bench_batch(F, ctx, args)
+        log("C4: batch %.3f s vs one at a time %.3f s (%.2fx), bit-exact %s"
+            % (batch["batch_s"], batch["alone_s"], batch["speedup"], batch["bit_exact_vs_alone"]))
+    ctx.close()
+    serve = None
+    if not args.no_serve:
+        serve = bench_serve(F, args)
+        log("C5: server %.3g draws/s p50 %.2f s p99 %.2f s; one at a time %.3g draws/s p50 %.2f s p99 %.2f s"
+            % (serve["server"]["draws_per_s"], serve["server"]["p50_s"], serve["server"]["p99_s"],
+               serve["one_at_a_time"]["draws_per_s"], serve["one_at_a_time"]["p50_s"],
+               serve["one_at_a_time"]["p99_s"]))
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(os.cpu_count() or 1, 16)
-        cpu = cpu_baseline(w, seed, 4 * threads, args.cpu_draws, threads)
+        cpu = cpu_baseline(w, seed, args.cpu_chains_per_thread * threads, args.cpu_draws, threads)
         log("cpu oracle: %.3g draws/s (%s)" % (cpu["value"], cpu["sample"]))
-    ctx.close()
 
     g = ess["gemm"]
     line = {
@@ -236,6 +432,8 @@ def main():
         "speedup_vs_sync_vmap": ess["sync"].get("vmap", {}).get("speedup_fsm"),
         "speedup_vs_sync_compact": ess["sync"].get("compact", {}).get("speedup_fsm"),
         "nuts": nuts,
+        "batch": batch,
+        "serve": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -216,8 +216,8 @@ fsmmc_status fsmmc_job_free(fsmmc_job* job);
 
 /* ---------------------------------------------------------------- batching
  * A batch steps several jobs together, possibly of different samplers,
- * targets, dimensions, chain counts and draw counts (ESS jobs in FP32 and
- * DRMH jobs).  One round is one replay of a captured hipGraph whose kernels
+ * targets, dimensions, chain counts and draw counts (FP32 jobs of any
+ * sampler).  One round is one replay of a captured hipGraph whose kernels
  * serve every job at once:
  *   - a grouped ellipse GEMM: the next `window` directions nu = L z of every
  *     ESS chain, all jobs' column blocks in one launch per tile shape;
@@ -225,7 +225,9 @@ fsmmc_status fsmmc_job_free(fsmmc_job* job);
  *     device queue, longest first -- one ESS chain for `window` draws, or 64
  *     DRMH chains (one per lane) for `dr_chunk` draws -- and run the chains'
  *     FSM steps (Sec. 3.2, Alg. "Vectorized FSM MCMC algorithm") without
- *     waiting for any other chain or job.
+ *     waiting for any other chain or job;
+ *   - `nuts_steps` NUTS runtime steps of every NUTS job: grouped transition,
+ *     per-job request compaction, grouped gradient tiles and reductions.
  * Chains of a job never synchronise with other jobs, and a job's draws are
  * bit-identical to running it alone with fsmmc_step_fsm.  While a job
  * belongs to a batch, the per-job stepping calls and fsmmc_job_free return
@@ -241,7 +243,8 @@ typedef struct {
     int32_t gemm_cols;       /* ellipse GEMM columns per block, 64 or 128 (0 = 64;
                                 128 applies to jobs with dim <= 512)                 */
     int32_t rounds_per_sync; /* graph replays between progress reads (0 = 4)         */
-    int32_t reserved[3];
+    int32_t nuts_steps;      /* NUTS runtime steps per round (0 = 16)                */
+    int32_t reserved[2];
 } fsmmc_batch_tune;
 
 typedef struct {
@@ -259,10 +262,10 @@ typedef struct {
 } fsmmc_batch_counters;
 
 /* Group n_jobs jobs of context ctx into a batch stepped on `stream`
- * (hipStream_t; NULL = a stream the batch creates).  The jobs must be ESS
- * (FP32) or DRMH jobs not already in a batch; their queued initialisation is
- * waited for.  Errors: EINVAL (null or repeated job, other context),
- * ENOTSUP (NUTS or FP64 job), EBUSY (job in another batch), EDEVICE. */
+ * (hipStream_t; NULL = a stream the batch creates).  The jobs must be FP32
+ * jobs not already in a batch; their queued initialisation is waited for.
+ * Errors: EINVAL (null or repeated job, other context, bad tuning value),
+ * ENOTSUP (FP64 job), EBUSY (job in another batch), EDEVICE. */
 fsmmc_status fsmmc_batch_create(fsmmc_ctx* ctx, fsmmc_job* const* jobs, int32_t n_jobs,
                                 void* stream, const fsmmc_batch_tune* tune,
                                 fsmmc_batch** out);
@@ -278,6 +281,83 @@ fsmmc_status fsmmc_batch_stats(fsmmc_batch* batch, fsmmc_batch_counters* out);
 
 /* Release the batch (not its jobs, which become free-standing again). */
 fsmmc_status fsmmc_batch_free(fsmmc_batch* batch);
+
+/* ---------------------------------------------------------------- serving
+ * A server runs sampling jobs submitted at any time, with continuous
+ * batching: a request loop in a thread of its own admits submitted jobs in
+ * arrival order as the context's HBM budget allows (their chain state is
+ * allocated on the device at admission and stays there), steps every
+ * admitted job together in the rounds of one shared batch, and retires a
+ * job as soon as its last chain has its last draw -- in the middle of the
+ * stream, while other jobs keep running -- which frees its memory for the
+ * next admission.  Because chains only meet their own job at its n-th draw
+ * (Sec. 3.2), retiring a job never waits for any other job.  A job's draws
+ * are bit-identical to running it alone with fsmmc_step_fsm. */
+typedef struct fsmmc_server fsmmc_server;
+
+typedef struct {
+    fsmmc_batch_tune batch; /* round shape of the shared batch (autotune is ignored)  */
+    int32_t ess_window;     /* direction buffer of an admitted ESS job, in draws per
+                               chain (0 = 16); bounds its memory to chains x window x
+                               dim floats                                             */
+    int32_t reserved[7];
+} fsmmc_server_config;
+
+/* One finished job, as reported by fsmmc_server_poll. */
+typedef struct {
+    uint64_t job_id;
+    int32_t status;   /* FSMMC_OK, or the error that ended the job (EBUDGET: the job
+                         alone exceeds the context's budget)                         */
+    int32_t reserved;
+    double t_submit;  /* fsmmc_clock() at submission, admission and completion        */
+    double t_admit;
+    double t_done;
+} fsmmc_server_done;
+
+typedef struct {
+    int64_t submitted, admitted, completed, failed;
+    int64_t rounds;      /* graph replays                                          */
+    int64_t draws;       /* draws produced, all jobs                               */
+    int32_t live_jobs;   /* admitted, not yet retired                              */
+    int32_t pending_jobs;/* submitted, waiting for admission                       */
+    int32_t peak_live_jobs;
+    int32_t reserved;
+    uint64_t peak_bytes; /* peak device bytes held by admitted jobs                */
+    double gpu_ms;       /* device time of the rounds                              */
+} fsmmc_server_counters;
+
+/* Monotonic host clock (seconds) the server stamps its records with. */
+double fsmmc_clock(void);
+
+/* Start a server on context ctx (its HBM budget bounds the admitted jobs'
+ * state).  cfg may be NULL.  Errors: EINVAL, EDEVICE. */
+fsmmc_status fsmmc_server_create(fsmmc_ctx* ctx, const fsmmc_server_config* cfg, fsmmc_server** out);
+
+/* Queue a job (same arguments as fsmmc_init_chains; FP32 only).  Returns at
+ * once with *job_id.  The target arrays and x0 must stay valid, and
+ * out_samples (device, n_chains x n_draws x dim, required) and out_counts
+ * (device, n_chains x n_draws int32 loop counts, or NULL) untouched, until
+ * the job is reported finished.  Errors: EINVAL, ENOTSUP (checked at once),
+ * EDEVICE (the server stopped after a device error). */
+fsmmc_status fsmmc_server_submit(fsmmc_server* srv, const fsmmc_target_spec* target,
+                                 const fsmmc_sampler_spec* sampler, int32_t n_chains,
+                                 int32_t n_draws, uint64_t seed, const void* x0,
+                                 void* out_samples, int32_t* out_counts, uint64_t* job_id);
+
+/* Move up to cap finished-job records into out (host array); *n_out
+ * receives how many.  Records are returned once, in completion order. */
+fsmmc_status fsmmc_server_poll(fsmmc_server* srv, fsmmc_server_done* out, int32_t cap,
+                               int32_t* n_out);
+
+/* Block until every submitted job has finished or timeout_s seconds have
+ * passed (timeout_s < 0: no limit); *idle (may be NULL) receives 1 if no
+ * job is pending or running. */
+fsmmc_status fsmmc_server_wait(fsmmc_server* srv, double timeout_s, int32_t* idle);
+
+fsmmc_status fsmmc_server_stats(fsmmc_server* srv, fsmmc_server_counters* out);
+
+/* Finish every submitted job, stop the request loop and release the server. */
+fsmmc_status fsmmc_server_destroy(fsmmc_server* srv);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char* fsmmc_last_error(void);

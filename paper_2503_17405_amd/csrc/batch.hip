@@ -1,8 +1,8 @@
-// batch.hip -- several jobs (different targets, dimensions, chain and draw
-// counts) stepped together, one captured hipGraph replay per round.
+// batch.hip -- several jobs (different samplers, targets, dimensions, chain
+// and draw counts) stepped together, one captured hipGraph replay per round.
 //
 // A round serves every job at once:
-//   1. batch_begin_kernel: reset the work queue and the per-job live counters;
+//   1. batch_begin_kernel: reset the work queue;
 //   2. batch_nu_kernel<RT, CT>: the grouped ellipse GEMM -- one launch per
 //      tile shape covers the next W directions of every ESS chain of every
 //      job (a table of (job, first column) tiles);
@@ -10,71 +10,85 @@
 //      device queue ordered longest first -- one ESS chain for W draws, or 64
 //      DRMH chains (one per lane) for `chunk` draws -- and runs the chains'
 //      FSM steps with the same device functions as the single-job kernels;
-//   4. batch_tally_kernel: chains still short of n, per job.
-// Because every random number is keyed by (seed, chain, draw, role, sub) and
-// every reduction has a fixed order, a job's draws do not depend on the
-// batch, the queue order or the tuning.
+//   4. nuts_steps NUTS runtime steps for every NUTS job: grouped transition
+//      (one wavefront per chain), per-job request compaction, grouped
+//      logistic-regression gradient tiles and grouped slice reductions;
+//   5. batch_tally_kernel: per job, chains short of n and draws so far.
+// Every random number is keyed by (seed, chain, draw, role, sub) and every
+// reduction has a fixed order, so a job's draws do not depend on the batch,
+// the queue order, the other jobs or the tuning.
 //
 // The autotuner measures real rounds (HIP events around each replay) for a
-// few values of W, the DRMH chunk and the GEMM column tile, scoring each by
-// the time the same work takes when each sampler class runs alone divided by
-// the measured round time, and keeps the best.
+// few values of W, the DRMH chunk and the GEMM column tile.  It scores a
+// configuration by the time the round's draws would take with each sampler
+// class running alone (measured once per class) divided by the measured
+// round time, and keeps the best.
 #include <algorithm>
 #include <cstring>
 #include <vector>
 
 #include "dr_device.h"
 #include "ess_device.h"
-#include "fsmmc_host.h"
+#include "logreg_device.h"
+#include "multi.h"
+#include "nuts_device.h"
 
 namespace fsmmc {
 
 enum BatchCls : int32_t {
     BC_ESS1 = 0, BC_ESS2, BC_ESS4, BC_ESS6, BC_ESS8, BC_ESS12, BC_ESS16,
-    BC_DR4, BC_DR8, BC_DR12, BC_DR16, BC_NONE
+    BC_DR4, BC_DR8, BC_DR12, BC_DR16, BC_NUTS, BC_NONE
 };
 
 struct BJob {
     int32_t cls;
     uint32_t chunk;  // DRMH draws per chain per round
+    int32_t m, n;
+    const uint32_t* t;  // chain draw counters
+    int32_t* list;      // NUTS request list and count
+    int32_t* count;
     unsigned long long* ctr;
     EssK<float> ess;
     NuK<float> nu;
     DrK dr;
+    NutsK nuts;
+    GradK grad;
+    ReduceK red;
 };
 
 struct BItem {
-    int32_t job, first;  // ESS: chain; DRMH: first of 64 chains
+    int32_t job, first;  // ESS: chain; DRMH: first of 64 chains; NUTS: chain / first of 4
 };
 
 struct BTile {
     int32_t job, col0;
 };
 
+struct BGrad {
+    int32_t job, ct, sl, pad;
+};
+
 struct BHdr {
     uint32_t next;  // work queue head
     uint32_t pad;
-    unsigned long long draws_ess, draws_dr;  // draws since the last host reset
-    unsigned long long live;                 // chains short of n after the round
+    unsigned long long live;       // chains short of n after the round
+    unsigned long long fsm_draws;  // draws emitted by the persistent FSM kernel
 };
 
-__global__ void batch_begin_kernel(BHdr* h, const BJob* jobs, int njobs)
-{
-    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (i == 0) {
-        h->next = 0;
-        h->live = 0;
-    }
-    if (i < njobs) {
-        jobs[i].ctr[3] = 0;
-        jobs[i].ctr[4] = 0;
-    }
-}
+struct BJobStat {
+    unsigned long long live, draws;
+};
 
-__global__ void batch_reset_kernel(BHdr* h)
+// The job table is read through the constant address space: the compiler may
+// then reload a view's fields where needed instead of holding the whole view
+// in registers across a chain's loop.
+typedef const BJob __attribute__((address_space(4))) ConstBJob;
+
+__global__ void batch_begin_kernel(BHdr* h)
 {
-    h->draws_ess = 0;
-    h->draws_dr = 0;
+    h->next = 0;
+    h->live = 0;
+    h->fsm_draws = 0;
 }
 
 template <int RT, int CT>
@@ -85,11 +99,6 @@ __global__ __launch_bounds__(512) void batch_nu_kernel(const BJob* jobs, const B
     nu_gemm_block<RT, CT>(a, t.col0);
 }
 
-// The job table is read through the constant address space: the compiler may
-// then reload a view's fields where needed instead of holding the whole view
-// in registers across the chain's loop.
-typedef const BJob __attribute__((address_space(4))) ConstBJob;
-
 // WIDE: include the DRMH body for dim 13..16 (more registers per lane, one
 // fewer wave per SIMD); instantiated only for batches that hold such a job.
 template <bool WIDE>
@@ -97,7 +106,7 @@ __global__ __launch_bounds__(256) void batch_fsm_kernel(const BJob* jobs_in, con
 {
     const ConstBJob* jobs = (const ConstBJob*)jobs_in;
     const int lane = threadIdx.x & 63;
-    unsigned long long de = 0, dd = 0;
+    unsigned long long nd = 0;  // draws emitted by this lane's chains (ESS: lane 0 counts)
     for (;;) {
         uint32_t it = 0;
         if (lane == 0) it = atomicAdd(&h->next, 1u);
@@ -110,46 +119,99 @@ __global__ __launch_bounds__(256) void batch_fsm_kernel(const BJob* jobs_in, con
         const int cls = jobs[item.job].cls;
         if (cls <= BC_ESS16) {
             const EssK<float>& a = *(const EssK<float>*)&jobs[item.job].ess;
-            uint32_t nd = 0;
+            uint32_t de = 0;
             switch (cls) {
-            case BC_ESS1: nd = ess_window<float, 1>(a, item.first, lane); break;
-            case BC_ESS2: nd = ess_window<float, 2>(a, item.first, lane); break;
-            case BC_ESS4: nd = ess_window<float, 4>(a, item.first, lane); break;
-            case BC_ESS6: nd = ess_window<float, 6>(a, item.first, lane); break;
-            case BC_ESS8: nd = ess_window<float, 8>(a, item.first, lane); break;
-            case BC_ESS12: nd = ess_window<float, 12>(a, item.first, lane); break;
-            default: nd = ess_window<float, 16>(a, item.first, lane); break;
+            case BC_ESS1: de = ess_window<float, 1>(a, item.first, lane); break;
+            case BC_ESS2: de = ess_window<float, 2>(a, item.first, lane); break;
+            case BC_ESS4: de = ess_window<float, 4>(a, item.first, lane); break;
+            case BC_ESS6: de = ess_window<float, 6>(a, item.first, lane); break;
+            case BC_ESS8: de = ess_window<float, 8>(a, item.first, lane); break;
+            case BC_ESS12: de = ess_window<float, 12>(a, item.first, lane); break;
+            default: de = ess_window<float, 16>(a, item.first, lane); break;
             }
-            if (lane == 0) de += nd;
+            if (lane == 0) nd += de;
         } else if (cls <= BC_DR16) {
             const DrK& a = *(const DrK*)&jobs[item.job].dr;
             const int c = item.first + lane;
             if (c < a.m) {
                 const uint32_t stop = a.t[c] + jobs[item.job].chunk;
                 if (cls == BC_DR4)
-                    dd += dr_run<4>(a, c, stop);
+                    nd += dr_run<4>(a, c, stop);
                 else if (cls == BC_DR8)
-                    dd += dr_run<8>(a, c, stop);
+                    nd += dr_run<8>(a, c, stop);
                 else if (!WIDE || cls == BC_DR12)
-                    dd += dr_run<12>(a, c, stop);
+                    nd += dr_run<12>(a, c, stop);
                 else
-                    dd += dr_run<WIDE ? 16 : 12>(a, c, stop);
+                    nd += dr_run<WIDE ? 16 : 12>(a, c, stop);
             }
         }
     }
-    if (de) atomicAdd(&h->draws_ess, de);
-    if (dd) atomicAdd(&h->draws_dr, dd);
+    if (nd) atomicAdd(&h->fsm_draws, nd);
 }
 
-__global__ void batch_tally_kernel(BHdr* h, const BJob* jobs, int njobs, unsigned long long* jlive)
+// NUTS: one wavefront per chain of the item table.
+template <int EPL>
+__global__ __launch_bounds__(256) void batch_nuts_step_kernel(const BJob* jobs_in, const BItem* items, int n)
 {
-    unsigned long long s = 0;
-    for (int i = threadIdx.x; i < njobs; i += blockDim.x) {
-        const unsigned long long v = jobs[i].ctr[4];
-        jlive[i] = v;
-        s += v;
+    const ConstBJob* jobs = (const ConstBJob*)jobs_in;
+    const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    if (w >= n) return;
+    BItem it = items[w];
+    it.job = __builtin_amdgcn_readfirstlane(it.job);
+    it.first = __builtin_amdgcn_readfirstlane(it.first);
+    const NutsK& a = *(const NutsK*)&jobs[it.job].nuts;
+    nuts_chain_step<EPL>(a, it.first, threadIdx.x & 63);
+}
+
+__global__ __launch_bounds__(1024) void batch_nuts_compact_kernel(const BJob* jobs, const int32_t* njobs)
+{
+    const BJob& J = jobs[njobs[blockIdx.x]];
+    nuts_compact_block(J.nuts.req, J.m, 0, J.list, J.count, J.ctr);
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void batch_grad_kernel(const BJob* jobs_in, const BGrad* tiles)
+{
+    const ConstBJob* jobs = (const ConstBJob*)jobs_in;
+    const BGrad t = tiles[blockIdx.x];
+    const GradK& a = *(const GradK*)&jobs[t.job].grad;
+    logreg_grad_tile<DT>(a, t.ct, t.sl);
+}
+
+// Four listed chains per block (one per wavefront).
+template <int EPL>
+__global__ __launch_bounds__(256) void batch_reduce_kernel(const BJob* jobs_in, const BItem* items)
+{
+    const ConstBJob* jobs = (const ConstBJob*)jobs_in;
+    const BItem it = items[blockIdx.x];
+    const ReduceK& a = *(const ReduceK*)&jobs[it.job].red;
+    logreg_reduce_one<EPL>(a, it.first + (int)(threadIdx.x >> 6), threadIdx.x & 63);
+}
+
+// Block i: job i's chains short of n and its draws so far.
+__global__ __launch_bounds__(256) void batch_tally_kernel(BHdr* h, const BJob* jobs, BJobStat* js)
+{
+    __shared__ unsigned long long s_live, s_draws;
+    if (threadIdx.x == 0) {
+        s_live = 0;
+        s_draws = 0;
     }
-    if (s) atomicAdd(&h->live, s);
+    __syncthreads();
+    const BJob& J = jobs[blockIdx.x];
+    unsigned long long live = 0, draws = 0;
+    for (int c = threadIdx.x; c < J.m; c += blockDim.x) {
+        const uint32_t t = J.t[c];
+        draws += t;
+        live += t < (uint32_t)J.n ? 1 : 0;
+    }
+    atomicAdd(&s_live, live);
+    atomicAdd(&s_draws, draws);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        js[blockIdx.x].live = s_live;
+        js[blockIdx.x].draws = s_draws;
+        if (s_live) atomicAdd(&h->live, s_live);
+    }
 }
 
 // ------------------------------------------------------------ host side
@@ -178,8 +240,6 @@ int dr_cls(int D)
     }
 }
 
-// Grouped GEMM launch shapes: (RT, CT) -> slot.
-constexpr int kTileSlots = 8;
 int tile_slot(int rt, int ct) { return (rt - 1) * 2 + (ct == 4 ? 1 : 0); }
 
 hipError_t launch_tiles(int slot, int ntiles, const BJob* jobs, const BTile* tiles, hipStream_t s)
@@ -197,48 +257,10 @@ hipError_t launch_tiles(int slot, int ntiles, const BJob* jobs, const BTile* til
     return hipGetLastError();
 }
 
-enum { MASK_ESS = 1, MASK_DR = 2 };
+int kind_slot(int kind) { return kind == FSMMC_ESS ? 0 : (kind == FSMMC_DRMH ? 1 : 2); }
+int kind_mask(int kind) { return kind == FSMMC_ESS ? MASK_ESS : (kind == FSMMC_DRMH ? MASK_DR : MASK_NUTS); }
 
-}  // namespace
-}  // namespace fsmmc
-
-using namespace fsmmc;
-
-struct fsmmc_batch {
-    fsmmc_ctx* ctx = nullptr;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    std::vector<fsmmc_job*> jobs;
-    std::vector<char> live;      // job still has chains short of n
-    std::vector<char> had_items; // job had work items in the current tables
-    fsmmc_batch_tune tune{};
-    int W = 16, chunk = 16, cols = 64, rps = 4;
-    int mask = MASK_ESS | MASK_DR;  // sampler classes given work items
-    bool tuned = false;
-    // device tables
-    BJob* d_jobs = nullptr;
-    BItem* d_items = nullptr;
-    size_t cap_items = 0;
-    BTile* d_tiles = nullptr;
-    size_t cap_tiles = 0;
-    unsigned char* d_stat = nullptr;  // BHdr, then live count per job
-    unsigned char* h_stat = nullptr;  // pinned mirror
-    int n_items = 0, fsm_blocks = 0;
-    int tile_off[kTileSlots] = {0}, tile_cnt[kTileSlots] = {0};
-    hipGraphExec_t exec = nullptr;
-    bool dirty = true;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    int max_resident = 0;  // workgroups of the FSM kernel resident at once
-    bool wide = false;     // a DRMH job has dim > 12
-    // statistics
-    int64_t rounds = 0, captures = 0, draws = 0;
-    double gpu_ms = 0.0, tune_ms = 0.0;
-    int trials = 0;
-};
-
-namespace {
-
-size_t stat_bytes(const fsmmc_batch* b) { return sizeof(BHdr) + b->jobs.size() * sizeof(unsigned long long); }
+size_t stat_bytes(size_t njobs) { return sizeof(BHdr) + njobs * sizeof(BJobStat); }
 
 void destroy_graph(fsmmc_batch* b)
 {
@@ -250,17 +272,46 @@ template <typename T>
 fsmmc_status ensure(T** p, size_t* cap, size_t n)
 {
     if (n <= *cap && *p) return FSMMC_OK;
+    const size_t want = std::max<size_t>(std::max<size_t>(n, 2 * *cap), 1);
     if (*p) (void)hipFree(*p);
     *p = nullptr;
     *cap = 0;
-    const size_t want = std::max<size_t>(n, 1);
     HIP_TRY(hipMalloc((void**)p, want * sizeof(T)));
     *cap = want;
     return FSMMC_OK;
 }
 
-// Rebuild the job views, the work queue and the tile tables for the live
-// jobs and the current configuration, then capture the round graph.
+fsmmc_status ensure_stat(fsmmc_batch* b, size_t njobs)
+{
+    const size_t need = stat_bytes(njobs);
+    if (need <= b->cap_stat && b->d_stat) return FSMMC_OK;
+    if (b->d_stat) (void)hipFree(b->d_stat);
+    if (b->h_stat) (void)hipHostFree(b->h_stat);
+    b->d_stat = nullptr;
+    b->h_stat = nullptr;
+    b->cap_stat = 0;
+    const size_t want = stat_bytes(std::max<size_t>(njobs, 16) * 2);
+    HIP_TRY(hipMalloc((void**)&b->d_stat, want));
+    HIP_TRY(hipHostMalloc((void**)&b->h_stat, want, hipHostMallocDefault));
+    b->cap_stat = want;
+    return FSMMC_OK;
+}
+
+template <typename T>
+fsmmc_status upload(T* dst, const std::vector<T>& v)
+{
+    if (!v.empty()) HIP_TRY(hipMemcpy(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return FSMMC_OK;
+}
+
+#define TRY_ST(expr)                           \
+    do {                                       \
+        fsmmc_status s__ = (expr);             \
+        if (s__ != FSMMC_OK) return s__;       \
+    } while (0)
+
+// Rebuild the job views and work tables for the live jobs and the current
+// configuration, then capture the round graph.
 fsmmc_status rebuild(fsmmc_batch* b)
 {
     HIP_TRY(hipStreamSynchronize(b->stream));  // no replay may still read the old tables
@@ -268,41 +319,55 @@ fsmmc_status rebuild(fsmmc_batch* b)
     std::vector<BJob> jv(nj);
     std::vector<std::pair<double, BItem>> items;
     std::vector<BTile> tiles[kTileSlots];
+    std::vector<BItem> nsteps[2], nred[2];
+    std::vector<BGrad> grads[2];
+    std::vector<int32_t> njobs;
     for (int i = 0; i < nj; ++i) {
         JobDev& d = b->jobs[i]->d;
         BJob& J = jv[i];
         std::memset(&J, 0, sizeof(J));
         J.ctr = d.ctr;
+        J.m = d.m;
+        J.n = d.n;
+        J.t = d.t;
         J.chunk = (uint32_t)b->chunk;
-        b->had_items[i] = 0;
+        J.cls = BC_NONE;
+        const bool on = b->live[i] && (b->mask & kind_mask(d.kind));
+        b->had_items[i] = on ? 1 : 0;
         if (d.kind == FSMMC_ESS) {
             d.W = std::max(1, std::min(b->W, d.Wcap));
-            J.cls = ess_cls(d.EPL);
+            d.nu_cur = 0;  // the grouped GEMM fills buffer 0
             J.ess = ess_view<float>(d);
             J.nu = ess_window_view<float>(d);
-            if (!b->live[i] || !(b->mask & MASK_ESS)) {
-                J.cls = BC_NONE;
-                continue;
-            }
-            b->had_items[i] = 1;
+            if (!on) continue;
+            J.cls = ess_cls(d.EPL);
             const double cost = (double)d.W * (d.EPL + 2);
             for (int c = 0; c < d.m; ++c) items.push_back({cost, BItem{i, c}});
             const int rt = ess_gemm_rt(d.Dp);
             const int ct = (b->cols == 128 && rt <= 2) ? 4 : 2;
-            const int nc = 32 * ct;
             const int ncols = d.m * d.W;
-            for (int c0 = 0; c0 < ncols; c0 += nc) tiles[tile_slot(rt, ct)].push_back(BTile{i, c0});
-        } else {
-            J.cls = dr_cls(d.D);
+            for (int c0 = 0; c0 < ncols; c0 += 32 * ct) tiles[tile_slot(rt, ct)].push_back(BTile{i, c0});
+        } else if (d.kind == FSMMC_DRMH) {
             J.dr = dr_view(d);
-            if (!b->live[i] || !(b->mask & MASK_DR)) {
-                J.cls = BC_NONE;
-                continue;
-            }
-            b->had_items[i] = 1;
+            if (!on) continue;
+            J.cls = dr_cls(d.D);
             // 64 chains, one per lane: per draw a few stages of NM/4 Philox blocks each
             const double cost = (double)b->chunk * (dr_nm(d.D) / 4 + 1);
             for (int c = 0; c < d.m; c += 64) items.push_back({cost, BItem{i, c}});
+        } else {
+            J.nuts = nuts_view(d, 0, 0);
+            J.grad = grad_view(d, 0);
+            J.red = reduce_view(d, 0, (float*)d.Gres, (float*)d.Ures, d.Dp);
+            J.list = d.list;
+            J.count = d.count;
+            if (!on) continue;
+            J.cls = BC_NUTS;
+            const int e = d.EPL == 1 ? 0 : 1;
+            for (int c = 0; c < d.m; ++c) nsteps[e].push_back(BItem{i, c});
+            for (int c = 0; c < d.m; c += 4) nred[e].push_back(BItem{i, c});
+            for (int ct = 0; ct * 64 < d.m; ++ct)
+                for (int sl = 0; sl < d.nslices; ++sl) grads[e].push_back(BGrad{i, ct, sl, 0});
+            njobs.push_back(i);
         }
     }
     std::stable_sort(items.begin(), items.end(),
@@ -317,41 +382,96 @@ fsmmc_status rebuild(fsmmc_batch* b)
         b->tile_cnt[s] = (int)tiles[s].size();
         tv.insert(tv.end(), tiles[s].begin(), tiles[s].end());
     }
-    fsmmc_status st = ensure(&b->d_items, &b->cap_items, iv.size());
-    if (st != FSMMC_OK) return st;
-    st = ensure(&b->d_tiles, &b->cap_tiles, tv.size());
-    if (st != FSMMC_OK) return st;
-    HIP_TRY(hipMemcpy(b->d_jobs, jv.data(), jv.size() * sizeof(BJob), hipMemcpyHostToDevice));
-    if (!iv.empty()) HIP_TRY(hipMemcpy(b->d_items, iv.data(), iv.size() * sizeof(BItem), hipMemcpyHostToDevice));
-    if (!tv.empty()) HIP_TRY(hipMemcpy(b->d_tiles, tv.data(), tv.size() * sizeof(BTile), hipMemcpyHostToDevice));
+    std::vector<BItem> nv;
+    for (int e = 0; e < 2; ++e) {
+        b->nstep_cnt[e] = (int)nsteps[e].size();
+        nv.insert(nv.end(), nsteps[e].begin(), nsteps[e].end());
+    }
+    b->red_off = (int)nv.size();
+    for (int e = 0; e < 2; ++e) {
+        b->red_cnt[e] = (int)nred[e].size();
+        nv.insert(nv.end(), nred[e].begin(), nred[e].end());
+    }
+    std::vector<BGrad> gv;
+    for (int e = 0; e < 2; ++e) {
+        b->grad_cnt[e] = (int)grads[e].size();
+        gv.insert(gv.end(), grads[e].begin(), grads[e].end());
+    }
+    b->n_nuts = (int)njobs.size();
+    TRY_ST(ensure(&b->d_jobs, &b->cap_jobs, (size_t)nj));
+    TRY_ST(ensure(&b->d_items, &b->cap_items, iv.size()));
+    TRY_ST(ensure(&b->d_tiles, &b->cap_tiles, tv.size()));
+    TRY_ST(ensure(&b->d_nitems, &b->cap_nitems, nv.size()));
+    TRY_ST(ensure(&b->d_grads, &b->cap_grads, gv.size()));
+    TRY_ST(ensure(&b->d_njobs, &b->cap_njobs, njobs.size()));
+    TRY_ST(ensure_stat(b, (size_t)nj));
+    TRY_ST(upload(b->d_jobs, jv));
+    TRY_ST(upload(b->d_items, iv));
+    TRY_ST(upload(b->d_tiles, tv));
+    TRY_ST(upload(b->d_nitems, nv));
+    TRY_ST(upload(b->d_grads, gv));
+    TRY_ST(upload(b->d_njobs, njobs));
     b->n_items = (int)iv.size();
-    b->fsm_blocks = std::max(1, std::min(b->max_resident, (b->n_items + 3) / 4));
+    const int resident = b->max_resident[b->wide ? 1 : 0];
+    b->fsm_blocks = std::max(1, std::min(resident, (b->n_items + 3) / 4));
 
     destroy_graph(b);
     BHdr* h = reinterpret_cast<BHdr*>(b->d_stat);
-    unsigned long long* jl = reinterpret_cast<unsigned long long*>(b->d_stat + sizeof(BHdr));
-    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    BJobStat* js = reinterpret_cast<BJobStat*>(b->d_stat + sizeof(BHdr));
+    const BJob* jobs = b->d_jobs;
+    hipStream_t s = b->stream;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    hipLaunchKernelGGL(batch_begin_kernel, dim3((nj + 255) / 256), dim3(256), 0, b->stream, h,
-                       (const BJob*)b->d_jobs, nj);
-    e = hipGetLastError();
-    for (int s = 0; s < kTileSlots && e == hipSuccess; ++s)
-        if (b->tile_cnt[s] > 0) e = launch_tiles(s, b->tile_cnt[s], b->d_jobs, b->d_tiles + b->tile_off[s], b->stream);
+    auto chk = [&]() {
+        if (e == hipSuccess) e = hipGetLastError();
+    };
+    hipLaunchKernelGGL(batch_begin_kernel, dim3(1), dim3(1), 0, s, h);
+    chk();
+    for (int t = 0; t < kTileSlots && e == hipSuccess; ++t)
+        if (b->tile_cnt[t] > 0) e = launch_tiles(t, b->tile_cnt[t], jobs, b->d_tiles + b->tile_off[t], s);
     if (e == hipSuccess && b->n_items > 0) {
         if (b->wide)
-            hipLaunchKernelGGL(batch_fsm_kernel<true>, dim3(b->fsm_blocks), dim3(256), 0, b->stream,
-                               (const BJob*)b->d_jobs, (const BItem*)b->d_items, b->n_items, h);
+            hipLaunchKernelGGL(batch_fsm_kernel<true>, dim3(b->fsm_blocks), dim3(256), 0, s, jobs,
+                               (const BItem*)b->d_items, b->n_items, h);
         else
-            hipLaunchKernelGGL(batch_fsm_kernel<false>, dim3(b->fsm_blocks), dim3(256), 0, b->stream,
-                               (const BJob*)b->d_jobs, (const BItem*)b->d_items, b->n_items, h);
-        e = hipGetLastError();
+            hipLaunchKernelGGL(batch_fsm_kernel<false>, dim3(b->fsm_blocks), dim3(256), 0, s, jobs,
+                               (const BItem*)b->d_items, b->n_items, h);
+        chk();
     }
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(batch_tally_kernel, dim3(1), dim3(256), 0, b->stream, h, (const BJob*)b->d_jobs, nj, jl);
-        e = hipGetLastError();
+    for (int step = 0; step < b->nuts_steps && b->n_nuts > 0 && e == hipSuccess; ++step) {
+        const BItem* st1 = b->d_nitems;
+        const BItem* st2 = st1 + b->nstep_cnt[0];
+        if (b->nstep_cnt[0])
+            hipLaunchKernelGGL(batch_nuts_step_kernel<1>, dim3((b->nstep_cnt[0] + 3) / 4), dim3(256), 0, s, jobs,
+                               st1, b->nstep_cnt[0]);
+        if (b->nstep_cnt[1])
+            hipLaunchKernelGGL(batch_nuts_step_kernel<2>, dim3((b->nstep_cnt[1] + 3) / 4), dim3(256), 0, s, jobs,
+                               st2, b->nstep_cnt[1]);
+        chk();
+        hipLaunchKernelGGL(batch_nuts_compact_kernel, dim3(b->n_nuts), dim3(1024), 0, s, jobs,
+                           (const int32_t*)b->d_njobs);
+        chk();
+        if (b->grad_cnt[0])
+            hipLaunchKernelGGL(batch_grad_kernel<2>, dim3(b->grad_cnt[0]), dim3(256), 0, s, jobs,
+                               (const BGrad*)b->d_grads);
+        if (b->grad_cnt[1])
+            hipLaunchKernelGGL(batch_grad_kernel<4>, dim3(b->grad_cnt[1]), dim3(256), 0, s, jobs,
+                               (const BGrad*)b->d_grads + b->grad_cnt[0]);
+        chk();
+        const BItem* r1 = b->d_nitems + b->red_off;
+        if (b->red_cnt[0])
+            hipLaunchKernelGGL(batch_reduce_kernel<1>, dim3(b->red_cnt[0]), dim3(256), 0, s, jobs, r1);
+        if (b->red_cnt[1])
+            hipLaunchKernelGGL(batch_reduce_kernel<2>, dim3(b->red_cnt[1]), dim3(256), 0, s, jobs,
+                               r1 + b->red_cnt[0]);
+        chk();
+    }
+    if (e == hipSuccess && nj > 0) {
+        hipLaunchKernelGGL(batch_tally_kernel, dim3(nj), dim3(256), 0, s, h, jobs, js);
+        chk();
     }
     hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+    hipError_t e2 = hipStreamEndCapture(s, &g);
     if (e != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
         return hip_fail(e, "batch round capture");
@@ -368,52 +488,6 @@ fsmmc_status rebuild(fsmmc_batch* b)
     return FSMMC_OK;
 }
 
-struct RoundResult {
-    double ms = 0.0;
-    unsigned long long de = 0, dd = 0, live = 0;
-};
-
-// Replay the round graph k times; fold liveness into the job flags.
-fsmmc_status replay(fsmmc_batch* b, int k, RoundResult* r)
-{
-    if (b->dirty) {
-        fsmmc_status st = rebuild(b);
-        if (st != FSMMC_OK) return st;
-    }
-    BHdr* h = reinterpret_cast<BHdr*>(b->d_stat);
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, b->stream, h);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipEventRecord(b->e0, b->stream));
-    for (int i = 0; i < k; ++i) HIP_TRY(hipGraphLaunch(b->exec, b->stream));
-    HIP_TRY(hipEventRecord(b->e1, b->stream));
-    HIP_TRY(hipMemcpyAsync(b->h_stat, b->d_stat, stat_bytes(b), hipMemcpyDeviceToHost, b->stream));
-    HIP_TRY(hipStreamSynchronize(b->stream));
-    float ms = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&ms, b->e0, b->e1));
-    const BHdr* hh = reinterpret_cast<const BHdr*>(b->h_stat);
-    const unsigned long long* jl = reinterpret_cast<const unsigned long long*>(b->h_stat + sizeof(BHdr));
-    r->ms = ms;
-    r->de = hh->draws_ess;
-    r->dd = hh->draws_dr;
-    b->rounds += k;
-    b->gpu_ms += ms;
-    b->draws += (int64_t)(r->de + r->dd);
-    unsigned long long live = 0;
-    for (size_t i = 0; i < b->jobs.size(); ++i) {
-        if (!b->had_items[i]) {
-            if (b->live[i]) live += 1;  // not stepped this round: still pending
-            continue;
-        }
-        if (b->live[i] && jl[i] == 0) {
-            b->live[i] = 0;
-            b->dirty = true;
-        }
-        live += jl[i];
-    }
-    r->live = live;
-    return FSMMC_OK;
-}
-
 bool any_live(const fsmmc_batch* b, int kind)
 {
     for (size_t i = 0; i < b->jobs.size(); ++i)
@@ -421,12 +495,156 @@ bool any_live(const fsmmc_batch* b, int kind)
     return false;
 }
 
-// Online autotuning on real rounds (see the file comment).
-fsmmc_status autotune(fsmmc_batch* b)
+uint64_t host_draws(const fsmmc_job* j)
+{
+    std::vector<uint32_t> t(j->d.m);
+    if (hipMemcpy(t.data(), j->d.t, t.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) return 0;
+    uint64_t s = 0;
+    for (uint32_t v : t) s += v;
+    return s;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ internal API
+fsmmc_status batch_setup(fsmmc_batch* b, fsmmc_ctx* ctx, void* stream, const fsmmc_batch_tune* tune)
+{
+    if (tune && tune->gemm_cols != 0 && tune->gemm_cols != 64 && tune->gemm_cols != 128)
+        return fail(FSMMC_EINVAL, "gemm_cols must be 0, 64 or 128");
+    if (tune && (tune->window < 0 || tune->dr_chunk < 0 || tune->rounds_per_sync < 0 || tune->nuts_steps < 0))
+        return fail(FSMMC_EINVAL, "tuning values must be >= 0");
+    b->ctx = ctx;
+    if (tune) b->tune = *tune;
+    b->W = b->tune.window > 0 ? b->tune.window : 16;
+    b->chunk = b->tune.dr_chunk > 0 ? b->tune.dr_chunk : 16;
+    b->cols = b->tune.gemm_cols > 0 ? b->tune.gemm_cols : 64;
+    b->rps = b->tune.rounds_per_sync > 0 ? b->tune.rounds_per_sync : 4;
+    b->nuts_steps = b->tune.nuts_steps > 0 ? b->tune.nuts_steps : 16;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (stream) {
+        b->stream = (hipStream_t)stream;
+    } else {
+        HIP_TRY(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+        b->own_stream = true;
+    }
+    HIP_TRY(hipEventCreate(&b->e0));
+    HIP_TRY(hipEventCreate(&b->e1));
+    int nb0 = 0, nb1 = 0, cus = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb0, batch_fsm_kernel<false>, 256, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, batch_fsm_kernel<true>, 256, 0));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    b->max_resident[0] = std::max(1, nb0) * std::max(1, cus);
+    b->max_resident[1] = std::max(1, nb1) * std::max(1, cus);
+    return ensure_stat(b, 16);
+}
+
+fsmmc_status batch_admissible(const fsmmc_batch* b, const fsmmc_job* j)
+{
+    if (!j) return fail(FSMMC_EINVAL, "job is NULL");
+    if (j->ctx != b->ctx) return fail(FSMMC_EINVAL, "job belongs to another context");
+    if (j->batch) return fail(FSMMC_EBUSY, "job is already in a batch");
+    if (j->d.dtype != FSMMC_F32) return fail(FSMMC_ENOTSUP, "batches run FP32 jobs");
+    return FSMMC_OK;
+}
+
+fsmmc_status batch_add(fsmmc_batch* b, fsmmc_job* j)
+{
+    TRY_ST(batch_admissible(b, j));
+    HIP_TRY(hipStreamSynchronize(j->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    // every chain may run to n within a round: no step budget; NUTS chains run to n
+    HIP_TRY(fill_i64(j->d.budget, INT64_MAX, j->d.m, b->stream));
+    j->d.tstop = (uint32_t)j->d.n;
+    b->jobs.push_back(j);
+    b->live.push_back(1);
+    b->had_items.push_back(0);
+    b->tsum.push_back(host_draws(j));
+    b->wide |= j->d.kind == FSMMC_DRMH && dr_nm(j->d.D) > 12;
+    j->batch = b;
+    b->dirty = true;
+    return ensure_stat(b, b->jobs.size());
+}
+
+void batch_remove(fsmmc_batch* b, fsmmc_job* j)
+{
+    (void)hipStreamSynchronize(b->stream);
+    for (size_t i = 0; i < b->jobs.size(); ++i) {
+        if (b->jobs[i] != j) continue;
+        b->jobs.erase(b->jobs.begin() + i);
+        b->live.erase(b->live.begin() + i);
+        b->had_items.erase(b->had_items.begin() + i);
+        b->tsum.erase(b->tsum.begin() + i);
+        break;
+    }
+    if (j->batch == b) {
+        j->batch = nullptr;
+        if (j->d.kind == FSMMC_ESS && j->d.Wcap > 0) j->d.W = j->d.Wcap;
+    }
+    b->wide = false;
+    for (fsmmc_job* o : b->jobs) b->wide |= o->d.kind == FSMMC_DRMH && dr_nm(o->d.D) > 12;
+    b->dirty = true;
+}
+
+bool batch_job_live(const fsmmc_batch* b, const fsmmc_job* j)
+{
+    for (size_t i = 0; i < b->jobs.size(); ++i)
+        if (b->jobs[i] == j) return b->live[i] != 0;
+    return false;
+}
+
+fsmmc_status batch_launch(fsmmc_batch* b, int k)
+{
+    b->pending_k = 0;
+    if (b->jobs.empty()) return FSMMC_OK;
+    if (b->dirty) TRY_ST(rebuild(b));
+    HIP_TRY(hipEventRecord(b->e0, b->stream));
+    for (int i = 0; i < k; ++i) HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    HIP_TRY(hipEventRecord(b->e1, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->h_stat, b->d_stat, stat_bytes(b->jobs.size()), hipMemcpyDeviceToHost, b->stream));
+    b->pending_k = k;
+    return FSMMC_OK;
+}
+
+fsmmc_status batch_collect(fsmmc_batch* b, RoundResult* r)
+{
+    *r = RoundResult();
+    if (b->pending_k == 0) return FSMMC_OK;
+    const int k = b->pending_k;
+    b->pending_k = 0;
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, b->e0, b->e1));
+    const BJobStat* js = reinterpret_cast<const BJobStat*>(b->h_stat + sizeof(BHdr));
+    r->ms = ms;
+    r->fsm_draws = reinterpret_cast<const BHdr*>(b->h_stat)->fsm_draws;
+    b->rounds += k;
+    b->gpu_ms += ms;
+    for (size_t i = 0; i < b->jobs.size(); ++i) {
+        const uint64_t dd = js[i].draws - b->tsum[i];
+        b->tsum[i] = js[i].draws;
+        r->draws[kind_slot(b->jobs[i]->d.kind)] += dd;
+        b->draws += (int64_t)dd;
+        r->live += js[i].live;
+        if (b->live[i] && js[i].live == 0) {
+            b->live[i] = 0;
+            b->dirty = true;
+        }
+    }
+    return FSMMC_OK;
+}
+
+fsmmc_status batch_round(fsmmc_batch* b, int k, RoundResult* r)
+{
+    TRY_ST(batch_launch(b, k));
+    return batch_collect(b, r);
+}
+
+fsmmc_status batch_autotune(fsmmc_batch* b)
 {
     b->tuned = true;
-    const bool has_ess = any_live(b, FSMMC_ESS), has_dr = any_live(b, FSMMC_DRMH);
-    if (!has_ess && !has_dr) return FSMMC_OK;
+    const bool has[3] = {any_live(b, FSMMC_ESS), any_live(b, FSMMC_DRMH), any_live(b, FSMMC_NUTS)};
+    const int nclass = (int)has[0] + (int)has[1] + (int)has[2];
+    if (!has[0] && !has[1]) return FSMMC_OK;  // nothing to tune for NUTS alone
     int wmax = 1;
     bool small_d = false;
     for (size_t i = 0; i < b->jobs.size(); ++i) {
@@ -437,86 +655,89 @@ fsmmc_status autotune(fsmmc_batch* b)
         }
     }
     RoundResult r;
-    double we = 1.0, wd = 1.0;  // time per draw of each class when it runs alone
+    double w[3] = {1.0, 1.0, 1.0};  // device time per draw of each class running alone
     auto run1 = [&](int W, int chunk, int cols, int mask) -> fsmmc_status {
         if (W != b->W || chunk != b->chunk || cols != b->cols || mask != b->mask) b->dirty = true;
         b->W = W;
         b->chunk = chunk;
         b->cols = cols;
         b->mask = mask;
-        fsmmc_status st = replay(b, 1, &r);
+        fsmmc_status st = batch_round(b, 1, &r);
         b->tune_ms += r.ms;
         b->trials++;
         return st;
     };
-    fsmmc_status st;
-    if (has_ess && has_dr) {
-        st = run1(16, 16, 64, MASK_ESS);
-        if (st != FSMMC_OK) return st;
-        if (r.de) we = r.ms / (double)r.de;
-        st = run1(16, 16, 64, MASK_DR);
-        if (st != FSMMC_OK) return st;
-        if (r.dd) wd = r.ms / (double)r.dd;
+    if (nclass > 1) {
+        const int masks[3] = {MASK_ESS, MASK_DR, MASK_NUTS};
+        for (int c = 0; c < 3; ++c) {
+            if (!has[c]) continue;
+            TRY_ST(run1(16, 16, 64, masks[c]));
+            if (r.draws[c]) w[c] = r.ms / (double)r.draws[c];
+        }
     }
-    auto score = [&]() { return r.ms > 0.0 ? (we * (double)r.de + wd * (double)r.dd) / r.ms : 0.0; };
+    auto score = [&]() {
+        double s = 0.0;
+        for (int c = 0; c < 3; ++c) s += w[c] * (double)r.draws[c];
+        return r.ms > 0.0 ? s / r.ms : 0.0;
+    };
     int bestW = b->W, bestC = b->chunk, bestCols = 64;
     double best = -1.0;
-    if (has_ess) {
+    if (has[0]) {
         for (int W : {8, 16, 32, 64}) {
             if (W > std::max(8, wmax)) break;
-            st = run1(W, W, 64, MASK_ESS | MASK_DR);
-            if (st != FSMMC_OK) return st;
+            TRY_ST(run1(W, W, 64, MASK_ALL));
             const double sc = score();
             if (sc > best) best = sc, bestW = W, bestC = W;
         }
     }
-    if (has_dr) {
-        const int base = has_ess ? bestW : 16;
+    if (has[1]) {
+        const int base = has[0] ? bestW : 16;
         for (int f : {1, 2, 4, 8}) {
-            const int chunk = has_ess ? std::max(1, base * f / 2) : base * f;
-            if (has_ess && chunk == bestC) continue;
-            st = run1(bestW, chunk, 64, MASK_ESS | MASK_DR);
-            if (st != FSMMC_OK) return st;
+            const int chunk = has[0] ? std::max(1, base * f / 2) : base * f;
+            if (has[0] && chunk == bestC) continue;
+            TRY_ST(run1(bestW, chunk, 64, MASK_ALL));
             const double sc = score();
             if (sc > best) best = sc, bestC = chunk;
         }
     }
-    if (has_ess && small_d) {
-        st = run1(bestW, bestC, 128, MASK_ESS | MASK_DR);
-        if (st != FSMMC_OK) return st;
+    if (has[0] && small_d) {
+        TRY_ST(run1(bestW, bestC, 128, MASK_ALL));
         if (score() > best) bestCols = 128;
     }
     b->W = bestW;
     b->chunk = bestC;
     b->cols = bestCols;
-    b->mask = MASK_ESS | MASK_DR;
+    b->mask = MASK_ALL;
     b->dirty = true;
     return FSMMC_OK;
 }
 
-void batch_release(fsmmc_batch* b)
+void batch_teardown(fsmmc_batch* b)
 {
-    if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     destroy_graph(b);
-    for (fsmmc_job* j : b->jobs) {
-        if (j->batch == b) {
-            j->batch = nullptr;
-            j->d.W = j->d.Wcap > 0 ? j->d.Wcap : j->d.W;
-        }
-    }
+    while (!b->jobs.empty()) batch_remove(b, b->jobs.back());
+    destroy_graph(b);
     if (b->d_jobs) (void)hipFree(b->d_jobs);
     if (b->d_items) (void)hipFree(b->d_items);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_nitems) (void)hipFree(b->d_nitems);
+    if (b->d_grads) (void)hipFree(b->d_grads);
+    if (b->d_njobs) (void)hipFree(b->d_njobs);
     if (b->d_stat) (void)hipFree(b->d_stat);
     if (b->h_stat) (void)hipHostFree(b->h_stat);
     if (b->e0) (void)hipEventDestroy(b->e0);
     if (b->e1) (void)hipEventDestroy(b->e1);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
-    delete b;
+    b->d_jobs = nullptr;
+    b->d_stat = nullptr;
+    b->h_stat = nullptr;
+    b->stream = nullptr;
 }
 
-}  // namespace
+}  // namespace fsmmc
+
+using namespace fsmmc;
 
 extern "C" {
 
@@ -526,65 +747,20 @@ fsmmc_status fsmmc_batch_create(fsmmc_ctx* ctx, fsmmc_job* const* jobs, int32_t 
     if (!ctx || !jobs || !out) return fail(FSMMC_EINVAL, "ctx, jobs or out is NULL");
     *out = nullptr;
     if (n_jobs < 1) return fail(FSMMC_EINVAL, "n_jobs must be >= 1");
+    fsmmc_batch probe;
+    probe.ctx = ctx;
     for (int i = 0; i < n_jobs; ++i) {
-        fsmmc_job* j = jobs[i];
-        if (!j) return fail(FSMMC_EINVAL, "job is NULL");
-        if (j->ctx != ctx) return fail(FSMMC_EINVAL, "job belongs to another context");
-        if (j->batch) return fail(FSMMC_EBUSY, "job is already in a batch");
+        TRY_ST(batch_admissible(&probe, jobs[i]));
         for (int k = 0; k < i; ++k)
-            if (jobs[k] == j) return fail(FSMMC_EINVAL, "job listed twice");
-        if (j->d.kind == FSMMC_NUTS) return fail(FSMMC_ENOTSUP, "batches run ESS and DRMH jobs");
-        if (j->d.dtype != FSMMC_F32) return fail(FSMMC_ENOTSUP, "batches run FP32 jobs");
+            if (jobs[k] == jobs[i]) return fail(FSMMC_EINVAL, "job listed twice");
     }
-    if (tune && tune->gemm_cols != 0 && tune->gemm_cols != 64 && tune->gemm_cols != 128)
-        return fail(FSMMC_EINVAL, "gemm_cols must be 0, 64 or 128");
-    if (tune && (tune->window < 0 || tune->dr_chunk < 0 || tune->rounds_per_sync < 0))
-        return fail(FSMMC_EINVAL, "tuning values must be >= 0");
-    HIP_TRY(hipSetDevice(ctx->device));
     fsmmc_batch* b = new fsmmc_batch();
-    b->ctx = ctx;
-    if (tune) b->tune = *tune;
-    b->W = b->tune.window > 0 ? b->tune.window : 16;
-    b->chunk = b->tune.dr_chunk > 0 ? b->tune.dr_chunk : 16;
-    b->cols = b->tune.gemm_cols > 0 ? b->tune.gemm_cols : 64;
-    b->rps = b->tune.rounds_per_sync > 0 ? b->tune.rounds_per_sync : 4;
-    b->jobs.assign(jobs, jobs + n_jobs);
-    b->live.assign(n_jobs, 1);
-    b->had_items.assign(n_jobs, 0);
-    auto bail = [&](fsmmc_status s) {
-        batch_release(b);
-        return s;
-    };
-    hipError_t e = hipSuccess;
-    if (stream) {
-        b->stream = (hipStream_t)stream;
-    } else {
-        e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
-        if (e != hipSuccess) return bail(hip_fail(e, "hipStreamCreateWithFlags"));
-        b->own_stream = true;
-    }
-    for (fsmmc_job* j : b->jobs) {
-        e = hipStreamSynchronize(j->stream);
-        if (e != hipSuccess) return bail(hip_fail(e, "hipStreamSynchronize"));
-    }
-    if ((e = hipMalloc((void**)&b->d_jobs, (size_t)n_jobs * sizeof(BJob))) != hipSuccess ||
-        (e = hipMalloc((void**)&b->d_stat, stat_bytes(b))) != hipSuccess ||
-        (e = hipHostMalloc((void**)&b->h_stat, stat_bytes(b), hipHostMallocDefault)) != hipSuccess ||
-        (e = hipEventCreate(&b->e0)) != hipSuccess || (e = hipEventCreate(&b->e1)) != hipSuccess)
-        return bail(hip_fail(e, "batch allocation"));
-    for (fsmmc_job* j : b->jobs) b->wide |= j->d.kind == FSMMC_DRMH && dr_nm(j->d.D) > 12;
-    int nb = 0, cus = 0;
-    if ((e = b->wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_fsm_kernel<true>, 256, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_fsm_kernel<false>, 256, 0)) !=
-            hipSuccess ||
-        (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device)) != hipSuccess)
-        return bail(hip_fail(e, "occupancy query"));
-    b->max_resident = std::max(1, nb) * std::max(1, cus);
-    // every chain may run to n within a round's window: no step budget
-    for (fsmmc_job* j : b->jobs) {
-        e = fill_i64(j->d.budget, INT64_MAX, j->d.m, b->stream);
-        if (e != hipSuccess) return bail(hip_fail(e, "budget fill"));
-        j->batch = b;
+    fsmmc_status st = batch_setup(b, ctx, stream, tune);
+    for (int i = 0; i < n_jobs && st == FSMMC_OK; ++i) st = batch_add(b, jobs[i]);
+    if (st != FSMMC_OK) {
+        batch_teardown(b);
+        delete b;
+        return st;
     }
     *out = b;
     return FSMMC_OK;
@@ -597,22 +773,20 @@ fsmmc_status fsmmc_batch_run(fsmmc_batch* b, int64_t max_rounds, int32_t* all_do
     int64_t done_rounds = 0;
     if (b->tune.autotune && !b->tuned) {
         const int64_t before = b->rounds;
-        fsmmc_status st = autotune(b);
-        if (st != FSMMC_OK) return st;
+        TRY_ST(batch_autotune(b));
         done_rounds += b->rounds - before;
     }
-    RoundResult r;
     auto none_live = [&]() {
         for (char v : b->live)
             if (v) return false;
         return true;
     };
     bool finished = none_live();
+    RoundResult r;
     while (!finished && (max_rounds <= 0 || done_rounds < max_rounds)) {
         int k = b->rps;
         if (max_rounds > 0) k = (int)std::min<int64_t>(k, max_rounds - done_rounds);
-        fsmmc_status st = replay(b, k, &r);
-        if (st != FSMMC_OK) return st;
+        TRY_ST(batch_round(b, k, &r));
         done_rounds += k;
         finished = none_live();
     }
@@ -643,7 +817,8 @@ fsmmc_status fsmmc_batch_stats(fsmmc_batch* b, fsmmc_batch_counters* out)
 fsmmc_status fsmmc_batch_free(fsmmc_batch* b)
 {
     if (!b) return fail(FSMMC_EINVAL, "batch is NULL");
-    batch_release(b);
+    batch_teardown(b);
+    delete b;
     return FSMMC_OK;
 }
 

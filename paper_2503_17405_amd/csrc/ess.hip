@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void nu_gemm_simple_kernel(NuK<T> a)
     T* zs = reinterpret_cast<T*>(smem_raw);
     const int g = blockIdx.x;
     const int ch = g / a.W, w = g - ch * a.W;
-    const uint32_t draw = a.draw_fixed >= 0 ? (uint32_t)a.draw_fixed : a.t[ch] + (uint32_t)w;
+    const uint32_t draw = a.draw_fixed >= 0 ? (uint32_t)a.draw_fixed : a.t[ch] + a.tadd + (uint32_t)w;
     const bool valid = a.draw_fixed >= 0 || draw < (uint32_t)a.n;
     for (int b = threadIdx.x; b < (a.Dp >> 2); b += blockDim.x) {
         T z[4] = {T(0), T(0), T(0), T(0)};
@@ -199,6 +199,7 @@ static hipError_t prior_draw_t(const JobDev& j, hipStream_t s)
     a.seed = j.seed;
     a.role = ROLE_INIT;
     a.draw_fixed = 0;
+    a.tadd = 0;
     a.t = j.t;
     a.L = (const T*)j.L;
     a.out = (T*)j.x;
@@ -208,7 +209,25 @@ static hipError_t prior_draw_t(const JobDev& j, hipStream_t s)
 template <typename T>
 static hipError_t fill_window_t(const JobDev& j, hipStream_t s)
 {
-    return launch_nu<T>(j, ess_window_view<T>(j), j.m * j.W, s);
+    return launch_nu<T>(j, ess_window_view<T>(j, j.nu_cur), j.m * j.W, s);
+}
+
+template <typename T>
+static hipError_t fill_next_window_t(const JobDev& j, int buf, hipStream_t s)
+{
+    return launch_nu<T>(j, ess_window_view<T>(j, buf, j.tsnap, (uint32_t)j.W), j.m * j.W, s);
+}
+
+__global__ void copy_u32_kernel(uint32_t* dst, const uint32_t* src, int n)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) dst[i] = src[i];
+}
+
+hipError_t copy_u32(uint32_t* dst, const uint32_t* src, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(copy_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, dst, src, n);
+    return hipGetLastError();
 }
 
 // log L(x) of every chain's current state (wave per chain).
@@ -219,13 +238,13 @@ __global__ __launch_bounds__(256) void ess_loglik_kernel(EssK<T> a)
     const int j = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (j >= a.m) return;
     const T* xj = a.x + (size_t)j * a.Dp;
-    T acc = T(0);
+    T xr[EPL], yv[EPL];
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
-        const int d = e * 64 + lane;
-        const T term = ess_term(xj[d], a.y[d], a.target, a.inv2v);
-        acc += (d < a.D) ? term : T(0);
+        xr[e] = xj[e * 64 + lane];
+        yv[e] = a.y[e * 64 + lane];
     }
+    T acc = ess_lane_loglik<T, EPL>(xr, yv, lane, a.D, a.target, a.inv2v);
     acc = wave_sum(acc);
     if (lane == 0) a.lx[j] = acc;
 }
@@ -300,6 +319,11 @@ hipError_t ess_prior_draw(const JobDev& j, const void* x0, hipStream_t s)
 hipError_t ess_fill_window(const JobDev& j, hipStream_t s)
 {
     return (j.dtype == FSMMC_F32) ? fill_window_t<float>(j, s) : fill_window_t<double>(j, s);
+}
+
+hipError_t ess_fill_next_window(const JobDev& j, int buf, hipStream_t s)
+{
+    return (j.dtype == FSMMC_F32) ? fill_next_window_t<float>(j, buf, s) : fill_next_window_t<double>(j, buf, s);
 }
 
 hipError_t ess_fsm_round(const JobDev& j, hipStream_t s)

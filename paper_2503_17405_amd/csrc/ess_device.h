@@ -19,8 +19,9 @@ struct NuK {
     int m, n, D, Dp, W;
     uint64_t seed;
     uint32_t role;
-    int draw_fixed;     // >= 0: every column uses this draw; < 0: draw = t[chain] + w
-    const uint32_t* t;  // chain draw counters
+    int draw_fixed;     // >= 0: every column uses this draw; < 0: draw = t[chain] + tadd + w
+    uint32_t tadd;      // offset of the window from t (the next window while this one runs)
+    const uint32_t* t;  // chain draw counters (or a snapshot of them)
     const T* L;         // Dp x Dp lower factor, zero padded
     T* out;             // column (chain, w) -> out[(chain * W + w) * Dp + row]
 };
@@ -46,19 +47,22 @@ struct EssK {
 // ------------------------------------------------------------ ellipse GEMM
 // One block of 8 waves computes NC = 32 CT columns (col0 ..) over all Dp rows.
 // Wave w owns RT row tiles of 32 rows in "snake" order (w, 15-w, 16+w, 31-w,
-// ...) so the triangular work is balanced across waves.  Per K chunk of 32:
-// the block draws its 32 x NC normals into LDS (one Philox block per thread
-// and 64 columns), then every wave multiplies its L rows (read as float4
-// along k from L2) by them.  The MFMA (32x32x2, FP32 accumulation) computes
-// nu^T = z^T L^T so each output register row is 32 consecutive nu entries of
-// one column (128-byte coalesced stores).  A block whose columns are all past
-// their chain's last draw exits at once.
+// ...) so the triangular work is balanced across waves.  The K dimension is
+// walked in chunks of 32, software-pipelined: while the MFMAs of chunk k run
+// (v_mfma_f32_32x32x2f32, FP32 accumulation, from the LDS tile of chunk k and
+// L rows read as float4 along k), each thread draws its normals of chunk k+1
+// (one Philox block per thread and 64 columns) into registers and stores them
+// into the other LDS buffer afterwards -- one barrier per chunk.  The MFMA
+// computes nu^T = z^T L^T so each output register row is 32 consecutive nu
+// entries of one column (128-byte coalesced stores).  The products and their
+// order per output element do not depend on the pipelining.  A block whose
+// columns are all past their chain's last draw exits at once.
 template <int RT, int CT = 2>
 __device__ __forceinline__ void nu_gemm_block(const NuK<float>& a, int col0)
 {
     static_assert(CT == 2 || CT == 4, "64 or 128 columns per block");
     constexpr int NC = 32 * CT, ZC = CT / 2;
-    __shared__ float Zs[32][NC];
+    __shared__ float Zs[2][32][NC];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, l32 = lane & 31;
     const int ncols = a.m * a.W;
@@ -77,12 +81,34 @@ __device__ __forceinline__ void nu_gemm_block(const NuK<float>& a, int col0)
         if (zvalid[cc]) {
             zchain[cc] = gcol / a.W;
             const int zw = gcol - zchain[cc] * a.W;
-            zdraw[cc] = a.draw_fixed >= 0 ? (uint32_t)a.draw_fixed : a.t[zchain[cc]] + (uint32_t)zw;
+            zdraw[cc] = a.draw_fixed >= 0 ? (uint32_t)a.draw_fixed : a.t[zchain[cc]] + a.tadd + (uint32_t)zw;
             zvalid[cc] = a.draw_fixed >= 0 || zdraw[cc] < (uint32_t)a.n;
         }
         any |= zvalid[cc] ? 1 : 0;
     }
     if (!__syncthreads_or(any)) return;
+
+    // this thread's 4 normals (rows 4 zb .. 4 zb + 3 of chunk kc) per column group
+    auto draw = [&](int kc, float (&z)[ZC][4]) {
+        const int kb = kc + 4 * zb;
+#pragma unroll
+        for (int cc = 0; cc < ZC; ++cc) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) z[cc][i] = 0.0f;
+            if (zvalid[cc] && kb < a.D) {
+                normals4<float>(a.seed, (uint32_t)zchain[cc], zdraw[cc], a.role, 0, (uint32_t)(kb >> 2), z[cc]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (kb + i >= a.D) z[cc][i] = 0.0f;
+            }
+        }
+    };
+    auto put = [&](int buf, const float (&z)[ZC][4]) {
+#pragma unroll
+        for (int cc = 0; cc < ZC; ++cc)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Zs[buf][4 * zb + i][zc + 64 * cc] = z[cc][i];
+    };
 
     const int ntiles = a.Dp >> 5;
     int tiles[RT];
@@ -99,21 +125,17 @@ __device__ __forceinline__ void nu_gemm_block(const NuK<float>& a, int col0)
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[r][c][q] = 0.0f;
 
+    {
+        float z0[ZC][4];
+        draw(0, z0);
+        put(0, z0);
+    }
+    __syncthreads();
+    int buf = 0;
     for (int kc = 0; kc < a.Dp; kc += 32) {
-        const int kb = kc + 4 * zb;
-#pragma unroll
-        for (int cc = 0; cc < ZC; ++cc) {
-            float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-            if (zvalid[cc] && kb < a.D) {
-                normals4<float>(a.seed, (uint32_t)zchain[cc], zdraw[cc], a.role, 0, (uint32_t)(kb >> 2), z);
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (kb + i >= a.D) z[i] = 0.0f;
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) Zs[4 * zb + i][zc + 64 * cc] = z[i];
-        }
-        __syncthreads();
+        float zn[ZC][4];
+        const bool more = kc + 32 < a.Dp;
+        if (more) draw(kc + 32, zn);
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
             const int ti = tiles[r];
@@ -133,12 +155,14 @@ __device__ __forceinline__ void nu_gemm_block(const NuK<float>& a, int col0)
             for (int kk = 0; kk < 16; ++kk) {
 #pragma unroll
                 for (int c = 0; c < CT; ++c) {
-                    const float av = Zs[16 * h + kk][c * 32 + l32];
+                    const float av = Zs[buf][16 * h + kk][c * 32 + l32];
                     acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, lr[kk], acc[r][c], 0, 0, 0);
                 }
             }
         }
+        if (more) put(buf ^ 1, zn);
         __syncthreads();
+        buf ^= 1;
     }
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
@@ -161,18 +185,49 @@ __device__ __forceinline__ void nu_gemm_block(const NuK<float>& a, int col0)
 }
 
 // ------------------------------------------------------------ ESS blocks
-template <typename T>
-__device__ __forceinline__ T ess_term(T f, T yv, int target, T inv2v)
+// Lane-local part of log L(f) over the lane's elements d = e * 64 + lane < D.
+//   Gaussian:  -sum (y - f)^2 / (2 sd^2)
+//   logistic:  sum y f - softplus(f), softplus(f) = max(f, 0) + log(1 + e^-|f|).
+// FP32 logistic takes the log of the product of the factors 1 + e^-|f|: each
+// lies in (1, 2], so the product of at most 16 cannot overflow, and one log
+// replaces EPL of them (the transcendental units bound this loop).
+template <typename T, int EPL>
+__device__ __forceinline__ T ess_lane_loglik(const T (&f)[EPL], const T (&yv)[EPL], int lane, int D, int target,
+                                             T inv2v)
 {
+    T acc = T(0);
     if (target == FSMMC_GP_GAUSS) {
-        const T r = yv - f;
-        return -(r * r) * inv2v;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+            const T r = yv[e] - f[e];
+            const T term = -(r * r) * inv2v;
+            acc += (e * 64 + lane < D) ? term : T(0);
+        }
+        return acc;
     }
-    return yv * f - M<T>::softplus(f);
+    if constexpr (sizeof(T) == 4) {
+        static_assert(EPL <= 16, "the factor product must stay below 2^16");
+        float prod = 1.0f;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+            const bool in = e * 64 + lane < D;
+            const float lin = yv[e] * f[e] - fmaxf(f[e], 0.0f);
+            acc += in ? lin : 0.0f;
+            prod *= in ? 1.0f + __expf(-fabsf(f[e])) : 1.0f;
+        }
+        return acc - __logf(prod);
+    } else {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+            const T term = yv[e] * f[e] - M<T>::softplus(f[e]);
+            acc += (e * 64 + lane < D) ? term : T(0);
+        }
+        return acc;
+    }
 }
 
 // x' = x cos(theta) + nu sin(theta) and log L(x'), summed in a fixed order
-// (lane-local over e, then a wave butterfly); the result is wave-uniform.
+// (lane-local, then a wave butterfly); the result is wave-uniform.
 template <typename T, int EPL>
 __device__ __forceinline__ T ess_propose_eval(const T (&x)[EPL], const T (&nu)[EPL], T (&xp)[EPL],
                                               const T (&yv)[EPL], T theta, int lane, int D, int target,
@@ -180,15 +235,9 @@ __device__ __forceinline__ T ess_propose_eval(const T (&x)[EPL], const T (&nu)[E
 {
     T s, c;
     M<T>::sincos_(theta, &s, &c);
-    T acc = T(0);
 #pragma unroll
-    for (int e = 0; e < EPL; ++e) {
-        const T f = M<T>::fma_(x[e], c, nu[e] * s);
-        xp[e] = f;
-        const T term = ess_term(f, yv[e], target, inv2v);
-        acc += (e * 64 + lane < D) ? term : T(0);
-    }
-    return wave_sum(acc);
+    for (int e = 0; e < EPL; ++e) xp[e] = M<T>::fma_(x[e], c, nu[e] * s);
+    return wave_sum(ess_lane_loglik<T, EPL>(xp, yv, lane, D, target, inv2v));
 }
 
 // INIT: threshold log y = log L(x) + log u and the initial bracket.
@@ -323,7 +372,7 @@ inline EssK<T> ess_view(const JobDev& j)
     a.seed = j.seed;
     a.inv2v = (j.target == FSMMC_GP_GAUSS) ? (T)(1.0 / (2.0 * j.noise_sd * j.noise_sd)) : T(0);
     a.y = (const T*)j.y;
-    a.nu = (const T*)j.nu;
+    a.nu = (const T*)j.nu + (size_t)j.nu_cur * j.m * j.Wcap * j.Dp;
     a.k = j.k;
     a.t = j.t;
     a.evals = j.evals;
@@ -342,9 +391,10 @@ inline EssK<T> ess_view(const JobDev& j)
     return a;
 }
 
-// Window product of the job's next W draws per chain.
+// Window product of the job's W draws per chain starting at t + tadd, into
+// direction buffer `buf` (t: the chains' counters or a snapshot of them).
 template <typename T>
-inline NuK<T> ess_window_view(const JobDev& j)
+inline NuK<T> ess_window_view(const JobDev& j, int buf = 0, const uint32_t* t = nullptr, uint32_t tadd = 0)
 {
     NuK<T> a;
     a.m = j.m;
@@ -355,9 +405,10 @@ inline NuK<T> ess_window_view(const JobDev& j)
     a.seed = j.seed;
     a.role = ROLE_NU;
     a.draw_fixed = -1;
-    a.t = j.t;
+    a.tadd = tadd;
+    a.t = t ? t : j.t;
     a.L = (const T*)j.L;
-    a.out = (T*)j.nu;
+    a.out = (T*)j.nu + (size_t)buf * j.m * j.Wcap * j.Dp;
     return a;
 }
 

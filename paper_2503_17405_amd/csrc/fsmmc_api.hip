@@ -112,6 +112,12 @@ static void job_release(fsmmc_job* j)
         (void)hipEventDestroy(t.b);
     }
     for (hipEvent_t e : j->pool) (void)hipEventDestroy(e);
+    if (j->side) {
+        (void)hipStreamSynchronize(j->side);
+        (void)hipStreamDestroy(j->side);
+    }
+    if (j->ev_snap) (void)hipEventDestroy(j->ev_snap);
+    if (j->ev_gemm) (void)hipEventDestroy(j->ev_gemm);
     if (j->ctx) {
         j->ctx->used.fetch_sub(j->bytes);
         j->ctx->jobs.fetch_sub(1);
@@ -171,8 +177,10 @@ fsmmc_status fsmmc_ctx_destroy(fsmmc_ctx* ctx)
 
 size_t fsmmc_ctx_bytes_in_use(const fsmmc_ctx* ctx) { return ctx ? ctx->used.load() : 0; }
 
-static fsmmc_status validate(const fsmmc_target_spec* t, const fsmmc_sampler_spec* s, int32_t m,
-                             int32_t n)
+}  // extern "C"
+
+fsmmc_status fsmmc::validate_specs(const fsmmc_target_spec* t, const fsmmc_sampler_spec* s, int32_t m,
+                                   int32_t n)
 {
     if (!t || !s) return fail(FSMMC_EINVAL, "target or sampler spec is NULL");
     if (m < 1) return fail(FSMMC_EINVAL, "n_chains must be >= 1");
@@ -220,6 +228,8 @@ static fsmmc_status validate(const fsmmc_target_spec* t, const fsmmc_sampler_spe
 
 // Copy a dim x dim matrix (device, row-major) into a zero-padded Dp x Dp
 // lower-triangular device buffer (entries above the diagonal dropped).
+extern "C" {
+
 static fsmmc_status stage_lower(fsmmc_job* job, const void* src, int D, int Dp, size_t es, void* dst)
 {
     std::vector<unsigned char> h((size_t)D * D * es), p((size_t)Dp * Dp * es, 0);
@@ -238,7 +248,7 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
     if (!ctx) return fail(FSMMC_EINVAL, "ctx is NULL");
     if (!out) return fail(FSMMC_EINVAL, "out is NULL");
     *out = nullptr;
-    fsmmc_status st = validate(target, sampler, n_chains, n_draws);
+    fsmmc_status st = validate_specs(target, sampler, n_chains, n_draws);
     if (st != FSMMC_OK) return st;
     HIP_TRY(hipSetDevice(ctx->device));
 
@@ -301,7 +311,11 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
         d.W = std::max(1, std::min(W, d.n));
         while ((int64_t)d.W * d.m > (int64_t)1 << 30 && d.W > 1) d.W /= 2;
         d.Wcap = d.W;
-        ALLOC(d.nu, m * (size_t)d.W * Dp * es);
+        ALLOC(d.nu, 2 * m * (size_t)d.W * Dp * es);
+        ALLOC(d.tsnap, m * 4);
+        HIP_TRY_JOB(hipStreamCreateWithFlags(&job->side, hipStreamNonBlocking));
+        HIP_TRY_JOB(hipEventCreateWithFlags(&job->ev_snap, hipEventDisableTiming));
+        HIP_TRY_JOB(hipEventCreateWithFlags(&job->ev_gemm, hipEventDisableTiming));
         fsmmc_status s2 = stage_lower(job, target->chol_L, d.D, d.Dp, es, d.L);
         if (s2 != FSMMC_OK) {
             job_release(job);
@@ -433,6 +447,47 @@ static fsmmc_status nuts_run(fsmmc_job* job, int mode, int64_t max_steps, uint32
     return FSMMC_OK;
 }
 
+// ESS windows [t0 + kW, t0 + (k+1)W): while window k is stepped on the job's
+// stream, the ellipse GEMM of window k+1 runs on the side stream from a
+// snapshot of the draw counters taken at the start of window k (every chain
+// either completes window k or reaches n, so window k+1 starts at the
+// snapshot + W).  Directions are double-buffered.  mode < 0: FSM runtime;
+// otherwise synchronized (FSMMC_SYNC_VMAP / COMPACT) from draw t0 to t1.
+static fsmmc_status ess_windows(fsmmc_job* job, int mode, uint32_t t0, uint32_t t1, int K)
+{
+    JobDev& d = job->d;
+    hipStream_t s = job->stream;
+    d.nu_cur = 0;
+    HIP_TRY(launch(job, KC_G, [&] { return ess_fill_window(d, s); }));
+    for (int k = 0; k < K; ++k) {
+        const bool next = k + 1 < K;
+        if (next) {
+            HIP_TRY(copy_u32(d.tsnap, d.t, d.m, s));
+            HIP_TRY(hipEventRecord(job->ev_snap, s));
+            HIP_TRY(hipStreamWaitEvent(job->side, job->ev_snap, 0));
+            const int nb = (k + 1) & 1;
+            HIP_TRY(launch_on(job, job->side, KC_G, [&] { return ess_fill_next_window(d, nb, job->side); }));
+            HIP_TRY(hipEventRecord(job->ev_gemm, job->side));
+        }
+        d.nu_cur = k & 1;
+        if (mode < 0) {
+            HIP_TRY(hipMemsetAsync(d.ctr + 3, 0, 2 * sizeof(unsigned long long), s));
+            HIP_TRY(launch(job, KC_FSM, [&] { return ess_fsm_round(d, s); }));
+        } else {
+            const uint32_t w0 = t0 + (uint32_t)k * (uint32_t)d.W;
+            const uint32_t w1 = std::min(t1, w0 + (uint32_t)d.W);
+            for (uint32_t dr = w0; dr < w1; ++dr) {
+                HIP_TRY(launch(job, KC_SYNC, [&] { return ess_sync_draw(d, dr, dr - w0, s); }));
+                if (mode == FSMMC_SYNC_VMAP)
+                    HIP_TRY(launch(job, KC_PAD, [&] { return ess_pad_draw(d, dr, dr - w0, s); }));
+            }
+        }
+        if (next) HIP_TRY(hipStreamWaitEvent(s, job->ev_gemm, 0));
+    }
+    d.nu_cur = 0;
+    return FSMMC_OK;
+}
+
 fsmmc_status fsmmc_step_fsm(fsmmc_job* job, int64_t max_steps, int32_t* all_done)
 {
     if (!job) return fail(FSMMC_EINVAL, "job is NULL");
@@ -455,9 +510,25 @@ fsmmc_status fsmmc_step_fsm(fsmmc_job* job, int64_t max_steps, int32_t* all_done
         return FSMMC_OK;
     }
     const int64_t b = max_steps > 0 ? max_steps : INT64_MAX;
-    hipLaunchKernelGGL(fill_i64_kernel, dim3((d.m + 255) / 256), dim3(256), 0, job->stream, d.budget, b, d.m);
-    HIP_TRY(hipGetLastError());
+    HIP_TRY(fill_i64(d.budget, b, d.m, job->stream));
     job->launches++;
+    if (max_steps <= 0) {
+        // every chain runs to n: the number of windows is known up front
+        std::vector<uint32_t> t;
+        fsmmc_status s = progress(job, t, nullptr);
+        if (s != FSMMC_OK) return s;
+        uint32_t rem = 0;
+        for (uint32_t v : t) rem = std::max(rem, (uint32_t)d.n - std::min(v, (uint32_t)d.n));
+        const int K = (int)((rem + (uint32_t)d.W - 1) / (uint32_t)d.W);
+        if (K > 0) {
+            s = ess_windows(job, -1, 0, 0, K);
+            if (s != FSMMC_OK) return s;
+        }
+        s = read_ctr(job);
+        if (s != FSMMC_OK) return s;
+        if (all_done) *all_done = (K == 0 || job->h_ctr[4] == 0) ? 1 : 0;
+        return FSMMC_OK;
+    }
     unsigned long long active = 1;
     for (;;) {
         HIP_TRY(hipMemsetAsync(d.ctr + 3, 0, 2 * sizeof(unsigned long long), job->stream));
@@ -510,16 +581,10 @@ fsmmc_status fsmmc_step_synchronized(fsmmc_job* job, int32_t n_draws, int32_t mo
         if (all_done) *all_done = t1 >= (uint32_t)d.n ? 1 : 0;
         return FSMMC_OK;
     }
-    uint32_t wstart = t0;
-    for (uint32_t dr = t0; dr < t1; ++dr) {
-        if (dr == t0 || dr - wstart == (uint32_t)d.W) {
-            wstart = dr;
-            HIP_TRY(launch(job, KC_G, [&] { return ess_fill_window(d, job->stream); }));
-        }
-        const uint32_t slot = dr - wstart;
-        HIP_TRY(launch(job, KC_SYNC, [&] { return ess_sync_draw(d, dr, slot, job->stream); }));
-        if (mode == FSMMC_SYNC_VMAP)
-            HIP_TRY(launch(job, KC_PAD, [&] { return ess_pad_draw(d, dr, slot, job->stream); }));
+    if (t1 > t0) {
+        const int K = (int)((t1 - t0 + (uint32_t)d.W - 1) / (uint32_t)d.W);
+        fsmmc_status s2 = ess_windows(job, mode, t0, t1, K);
+        if (s2 != FSMMC_OK) return s2;
     }
     HIP_TRY(hipStreamSynchronize(job->stream));
     harvest(job);

@@ -31,6 +31,9 @@ fsmmc_status hip_fail(hipError_t e, const char* what);
         if (e__ != hipSuccess) return ::fsmmc::hip_fail(e__, #expr);   \
     } while (0)
 
+// Argument checks of fsmmc_init_chains (sets the error message).
+fsmmc_status validate_specs(const fsmmc_target_spec* t, const fsmmc_sampler_spec* s, int32_t m, int32_t n);
+
 hipError_t fill_i64(int64_t* p, int64_t v, int n, hipStream_t s);
 hipError_t fill_i32(int32_t* p, int32_t v, int n, hipStream_t s);
 
@@ -54,6 +57,10 @@ struct fsmmc_job {
     int launches = 0;
     uint32_t step = 0;  // NUTS runtime step counter (keys the per-step counters)
     fsmmc_batch* batch = nullptr;  // the batch or server that owns the job's stepping, if any
+    // ESS: the next window's ellipse GEMM runs on a side stream while the
+    // current window is stepped on `stream`
+    hipStream_t side = nullptr;
+    hipEvent_t ev_snap = nullptr, ev_gemm = nullptr;
     // optional per-launch device timing
     bool timing = false;
     std::vector<hipEvent_t> pool;
@@ -76,27 +83,33 @@ inline hipEvent_t ev_get(fsmmc_job* j)
     return e;
 }
 
-// Queue one launcher call; with timing on, bracket it with events.
+// Queue one launcher call on stream s; with timing on, bracket it with events.
 template <typename F>
-inline hipError_t launch(fsmmc_job* j, int cls, F&& fn)
+inline hipError_t launch_on(fsmmc_job* j, hipStream_t s, int cls, F&& fn)
 {
     hipEvent_t a = nullptr, b = nullptr;
     if (j->timing) {
         a = ev_get(j);
-        if (a) (void)hipEventRecord(a, j->stream);
+        if (a) (void)hipEventRecord(a, s);
     }
     hipError_t e = fn();
     j->launches++;
     if (j->timing && a) {
         b = ev_get(j);
         if (b) {
-            (void)hipEventRecord(b, j->stream);
+            (void)hipEventRecord(b, s);
             j->pending.push_back({a, b, cls});
         } else {
             j->pool.push_back(a);
         }
     }
     return e;
+}
+
+template <typename F>
+inline hipError_t launch(fsmmc_job* j, int cls, F&& fn)
+{
+    return launch_on(j, j->stream, cls, static_cast<F&&>(fn));
 }
 
 // After the stream has drained: fold the recorded intervals into the totals.

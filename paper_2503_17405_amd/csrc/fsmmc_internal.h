@@ -47,9 +47,11 @@ struct JobDev {
     void* tmin = nullptr;
     void* tmax = nullptr;
     void* logy = nullptr;
-    void* nu = nullptr;  // m x Wcap x Dp ellipse directions of the current window
+    void* nu = nullptr;  // 2 x m x Wcap x Dp ellipse directions (double-buffered windows)
     int W = 0;           // draws per window (<= Wcap)
-    int Wcap = 0;        // draws the direction buffer holds per chain
+    int Wcap = 0;        // draws one direction buffer holds per chain
+    int nu_cur = 0;      // buffer the stepping kernels read
+    uint32_t* tsnap = nullptr;  // m: draw counters at the start of the running window
 
     // NUTS
     int32_t* jd = nullptr;     // tree depth of the subtree being built
@@ -88,6 +90,9 @@ struct JobDev {
 // ESS launchers (ess.hip)
 hipError_t ess_prior_draw(const JobDev& j, const void* x0, hipStream_t s);
 hipError_t ess_fill_window(const JobDev& j, hipStream_t s);
+// Directions of the window after the running one (draws tsnap + W ..) into buffer buf.
+hipError_t ess_fill_next_window(const JobDev& j, int buf, hipStream_t s);
+hipError_t copy_u32(uint32_t* dst, const uint32_t* src, int n, hipStream_t s);
 hipError_t ess_fsm_round(const JobDev& j, hipStream_t s);
 hipError_t ess_sync_draw(const JobDev& j, uint32_t draw, uint32_t slot, hipStream_t s);
 hipError_t ess_pad_draw(const JobDev& j, uint32_t draw, uint32_t slot, hipStream_t s);

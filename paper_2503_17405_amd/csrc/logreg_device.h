@@ -1,0 +1,253 @@
+// logreg_device.h -- batched potential and gradient of Bayesian logistic
+// regression (the NUTS g), shared by the single-job kernels (logreg.hip) and
+// the grouped multi-job kernels (batch.hip).  Layout and tiling are described
+// in logreg.hip.
+#pragma once
+#include "fsmmc_device.h"
+#include "fsmmc_internal.h"
+
+namespace fsmmc {
+
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+struct GradK {
+    int m, N, Dp, slice_rows, nslices, dense;  // dense > 0: columns are chains 0 .. dense-1
+    const float* X;   // Np x Dp, zero padded
+    const float* y;   // Np
+    const float* Th;  // m x Dp, indexed by chain
+    const int32_t* list;
+    const int32_t* count;
+    float* Gpart;  // nslices x m x Dp (indexed by chain)
+    float* Upart;  // nslices x m
+};
+
+// One block (4 waves): listed chains 64 ct .. 64 ct + 63, row slice sl.
+template <int DT>
+__device__ __forceinline__ void logreg_grad_tile(const GradK& a, int ct, int sl)
+{
+
+    constexpr int DP = 32 * DT;   // padded dimension
+    constexpr int TP = DP + 4;    // LDS row pitch of Theta and X chunks
+    constexpr int RP = 64 + 4;    // LDS row pitch of r
+    constexpr int GT = DT / 2;    // 32 x 32 gradient tiles per wave
+    __shared__ float Ths[64 * TP];
+    __shared__ float Xs[2][32 * TP];
+    __shared__ float Rs[32 * RP];
+    __shared__ float Ured[4][64];
+    __shared__ int cols[64];
+
+    const int ncols = a.dense > 0 ? a.dense : *a.count;
+    if (ct * 64 >= ncols) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l16 = lane & 15, q4 = lane >> 4, l32 = lane & 31, h = lane >> 5;
+
+    if (tid < 64) {
+        const int g = ct * 64 + tid;
+        cols[tid] = g < ncols ? (a.dense > 0 ? g : a.list[g]) : -1;
+    }
+    __syncthreads();
+    for (int i = tid; i < 64 * DP; i += 256) {
+        const int col = i / DP, d = i - col * DP;
+        const int ch = cols[col];
+        Ths[col * TP + d] = ch >= 0 ? a.Th[(size_t)ch * DP + d] : 0.0f;
+    }
+
+    // roles
+    const int rt = wave & 1;          // eta row tile (16 rows)
+    const int et0 = 2 * (wave >> 1);  // eta chain tiles et0, et0 + 1 (16 chains each)
+    // gradient tiles (32 x 32): tile id = wave * GT + t, d tile id >> 1, chain tile id & 1
+    floatx16 accg[GT];
+#pragma unroll
+    for (int t = 0; t < GT; ++t)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) accg[t][q] = 0.0f;
+    float uacc[2] = {0.0f, 0.0f};
+
+    const int rb = sl * a.slice_rows;
+    const int re = min(rb + a.slice_rows, a.N);
+    const int nchunk = (re - rb + 31) / 32;
+    constexpr int V4 = 32 * DP / 4 / 256;  // float4 per thread per chunk
+    floatx4 stage[V4];
+    if (nchunk > 0) {
+        const floatx4* src = reinterpret_cast<const floatx4*>(a.X + (size_t)rb * DP);
+#pragma unroll
+        for (int v = 0; v < V4; ++v) {
+            const int f = tid + 256 * v, row = f / (DP / 4), c4 = f - row * (DP / 4);
+            *reinterpret_cast<floatx4*>(&Xs[0][row * TP + 4 * c4]) = src[f];
+        }
+    }
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nchunk) {
+            const floatx4* src = reinterpret_cast<const floatx4*>(a.X + (size_t)(rb + 32 * (ch + 1)) * DP);
+#pragma unroll
+            for (int v = 0; v < V4; ++v) stage[v] = src[tid + 256 * v];
+        }
+        __syncthreads();  // chunk ch in Xs[buf]; previous chunk's Rs and Xs[buf ^ 1] no longer read
+        const float* X = Xs[buf];
+        // 1. eta tiles (16 x 16), K = DP in steps of 4
+        floatx4 e0 = {0.0f, 0.0f, 0.0f, 0.0f}, e1 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 8
+        for (int kk = 0; kk < DP / 4; ++kk) {
+            const int k = 4 * kk + q4;
+            const float xa = X[(16 * rt + l16) * TP + k];
+            const float b0 = Ths[(16 * et0 + l16) * TP + k];
+            const float b1 = Ths[(16 * (et0 + 1) + l16) * TP + k];
+            e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa, b0, e0, 0, 0, 0);
+            e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa, b1, e1, 0, 0, 0);
+        }
+        // 2. r and the log-likelihood (lane: chain 16 et + l16, rows 4 q4 .. +3)
+        const int r0 = rb + 32 * ch;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const floatx4 e = t ? e1 : e0;
+            const int col = 16 * (et0 + t) + l16;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int lr = 16 * rt + 4 * q4 + i;  // row within the chunk
+                const int row = r0 + lr;
+                const bool ok = row < re;
+                const float v = e[i];
+                const float yv = a.y[row];
+                const float ex = __expf(-fabsf(v));
+                const float inv = __frcp_rn(1.0f + ex);
+                const float sig = v >= 0.0f ? inv : ex * inv;
+                const float sp = fmaxf(v, 0.0f) + __logf(1.0f + ex);
+                uacc[t] += ok ? (yv * v - sp) : 0.0f;
+                Rs[lr * RP + col] = ok ? (yv - sig) : 0.0f;
+            }
+        }
+        __syncthreads();  // r complete
+        // 3. gradient tiles, K = 32 rows in steps of 2
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk) {
+            const int row = 2 * kk + h;
+#pragma unroll
+            for (int t = 0; t < GT; ++t) {
+                const float xa = X[row * TP + 32 * ((wave * GT + t) >> 1) + l32];
+                const float rb_ = Rs[row * RP + 32 * ((wave * GT + t) & 1) + l32];
+                accg[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(xa, rb_, accg[t], 0, 0, 0);
+            }
+        }
+        if (ch + 1 < nchunk) {
+#pragma unroll
+            for (int v = 0; v < V4; ++v) {
+                const int f = tid + 256 * v, row = f / (DP / 4), c4 = f - row * (DP / 4);
+                *reinterpret_cast<floatx4*>(&Xs[buf ^ 1][row * TP + 4 * c4]) = stage[v];
+            }
+        }
+    }
+    // log-likelihood per chain: lanes of one column hold different rows
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        uacc[t] += __shfl_xor(uacc[t], 16, 64);
+        uacc[t] += __shfl_xor(uacc[t], 32, 64);
+    }
+    __syncthreads();  // all waves done with Xs / Rs
+    if (q4 == 0) {
+        Ured[wave][16 * et0 + l16] = uacc[0];
+        Ured[wave][16 * (et0 + 1) + l16] = uacc[1];
+    }
+    // gradient tiles -> LDS [d][chain] (reusing Ths) for coalesced stores
+    float* Red = Ths;
+#pragma unroll
+    for (int t = 0; t < GT; ++t)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int d = 32 * ((wave * GT + t) >> 1) + 8 * (q >> 2) + 4 * h + (q & 3);
+            const int col = 32 * ((wave * GT + t) & 1) + l32;
+            Red[col * TP + d] = accg[t][q];
+        }
+    __syncthreads();
+    for (int i = tid; i < 64 * DP; i += 256) {
+        const int col = i / DP, d = i - col * DP;
+        const int chn = cols[col];
+        if (chn >= 0) a.Gpart[((size_t)sl * a.m + chn) * DP + d] = Red[col * TP + d];
+    }
+    if (tid < 64 && cols[tid] >= 0) {
+        // waves 2k and 2k+1 cover the two row tiles of chains 32k .. 32k+31
+        const int w0 = (tid >> 5) * 2;
+        a.Upart[(size_t)sl * a.m + cols[tid]] = Ured[w0][tid] + Ured[w0 + 1][tid];
+    }
+}
+
+struct ReduceK {
+    int m, Dp, nslices, dense;
+    const float* Th;
+    const int32_t* list;
+    const int32_t* count;
+    const float* Gpart;
+    const float* Upart;
+    float* G;  // chain-indexed outputs, row stride gstride
+    float* U;
+    int gstride;
+};
+
+// grad U = theta - sum_s partial_s, U = |theta|^2/2 - sum_s loglik_s (slice order).
+template <int EPL>
+__device__ __forceinline__ void logreg_reduce_one(const ReduceK& a, int p, int lane)
+{
+
+    const int ncols = a.dense > 0 ? a.dense : *a.count;
+    if (p >= ncols) return;
+    const int c = a.dense > 0 ? p : a.list[p];
+    WaveVec<EPL> th, g;
+    th.load(a.Th + (size_t)c * a.Dp, lane);
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) g.r[e] = 0.0f;
+    for (int s = 0; s < a.nslices; ++s) {
+        const float* gp = a.Gpart + ((size_t)s * a.m + c) * a.Dp;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) g.r[e] += gp[e * 64 + lane];
+    }
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) g.r[e] = th.r[e] - g.r[e];
+    g.store(a.G + (size_t)c * a.gstride, lane);
+    float ll = 0.0f;
+    for (int s = 0; s < a.nslices; ++s) ll += a.Upart[(size_t)s * a.m + c];
+    const float U = 0.5f * wdot(th, th) - ll;
+    if (lane == 0) a.U[c] = U;
+}
+
+// Views of a NUTS job's gradient buffers.  dense > 0: the columns are chains
+// 0 .. dense-1 instead of the compacted request list.
+inline GradK grad_view(const JobDev& j, int dense)
+{
+    GradK g;
+    g.m = j.m;
+    g.N = j.N;
+    g.Dp = j.Dp;
+    g.slice_rows = j.slice_rows;
+    g.nslices = j.nslices;
+    g.dense = dense;
+    g.X = (const float*)j.X;
+    g.y = (const float*)j.y;
+    g.Th = (const float*)j.Thq;
+    g.list = j.list;
+    g.count = j.count;
+    g.Gpart = (float*)j.Gpart;
+    g.Upart = (float*)j.Upart;
+    return g;
+}
+
+inline ReduceK reduce_view(const JobDev& j, int dense, float* Gout, float* Uout, int gstride)
+{
+    ReduceK r;
+    r.m = j.m;
+    r.Dp = j.Dp;
+    r.nslices = j.nslices;
+    r.dense = dense;
+    r.Th = (const float*)j.Thq;
+    r.list = j.list;
+    r.count = j.count;
+    r.Gpart = (const float*)j.Gpart;
+    r.Upart = (const float*)j.Upart;
+    r.G = Gout;
+    r.U = Uout;
+    r.gstride = gstride;
+    return r;
+}
+
+}  // namespace fsmmc

@@ -23,47 +23,9 @@
 // Readings: multinomial leaf sampling inside a subtree, biased progressive
 // merge of subtrees, generalized U-turn criterion on every aligned sub-span,
 // divergence when H - H0 > 1000, identity mass.
-#include "fsmmc_device.h"
-#include "fsmmc_internal.h"
+#include "nuts_device.h"
 
 namespace fsmmc {
-
-typedef float floatx16 __attribute__((ext_vector_type(16)));
-
-enum NutsState : int32_t { NS_INIT = 1, NS_DOUBLE = 2, NS_INTEGRATE = 3, NS_CHECK = 4, NS_DONE = 5, NS_WAIT = 6 };
-enum NutsFlag : int32_t { NF_INVALID = 1, NF_STOP = 2, NF_DIVERGED = 4, NF_TURNED = 8, NF_PENDING = 16 };
-
-constexpr float kDeltaMax = 1000.0f;
-
-__device__ __forceinline__ float logaddexp_f(float a, float b)
-{
-    if (a == -INFINITY) return b;
-    if (b == -INFINITY) return a;
-    const float mx = fmaxf(a, b);
-    return mx + log1pf(expf(-fabsf(a - b)));
-}
-
-struct NutsK {
-    int m, n, D, Dp, J, nvec, ckp0, ckr0, mode;
-    uint32_t step, tstop;
-    uint64_t seed;
-    float eps;
-    int32_t *k, *jd, *v, *nn, *flags, *nleap;
-    uint32_t* t;
-    int64_t* budget;
-    float *H0, *W, *Ws, *UP, *US;
-    float* V;  // [chain][nvec][Dp]
-    float* Thq;
-    const float* Gres;
-    const float* Ures;
-    int32_t* req;
-    float* out;
-    int32_t* counts;
-    unsigned long long* ctr;
-    uint32_t* wctr;
-};
-
-enum { V_THL = 0, V_PL, V_GL, V_THR, V_PR, V_GR, V_THP, V_GP, V_THS, V_GS, V_RHO, V_RHOS, V_PH, V_FIXED };
 
 template <int EPL>
 __global__ __launch_bounds__(256) void nuts_step_kernel(NutsK a)
@@ -75,248 +37,13 @@ __global__ __launch_bounds__(256) void nuts_step_kernel(NutsK a)
         a.wctr[3 + (a.step + 1) % 3] = 0u;
     }
     if (c >= a.m) return;
-    uint32_t t = a.t[c];
-    if (t >= a.tstop) {
-        if (lane == 0) a.req[c] = 0;
-        return;
-    }
-    float* Vc = a.V + (size_t)c * a.nvec * a.Dp;
-    auto vec = [&](int i) { return Vc + (size_t)i * a.Dp; };
-    int k = a.k[c], j = a.jd[c], v = a.v[c], nn = a.nn[c], fl = a.flags[c], nleap = a.nleap[c];
-    int64_t budget = a.budget[c];
-    float H0 = a.H0[c], W = a.W[c], Ws = a.Ws[c], UP = a.UP[c], US = a.US[c];
-    const bool release = a.mode != 0 && a.wctr[(a.step + 2) % 3] == 0u;
-    const float he = 0.5f * a.eps;
-    int req = 0;
-    unsigned long long steps = 0;
-
-    // 1) the leapfrog whose gradient has arrived
-    if (fl & NF_PENDING) {
-        const int eth = v > 0 ? V_THR : V_THL, ep = v > 0 ? V_PR : V_PL, eg = v > 0 ? V_GR : V_GL;
-        const float vhe = (float)v * he;
-        WaveVec<EPL> g, p, ph;
-        g.load(a.Gres + (size_t)c * a.Dp, lane);
-        ph.load(vec(V_PH), lane);
-#pragma unroll
-        for (int e = 0; e < EPL; ++e) p.r[e] = ph.r[e] - vhe * g.r[e];
-        const float Un = a.Ures[c];
-        ++nleap;
-        const float w = H0 - (Un + 0.5f * wdot(p, p));
-        p.store(vec(ep), lane);
-        g.store(vec(eg), lane);
-        if (!(-w <= kDeltaMax)) {
-            fl |= NF_INVALID | NF_DIVERGED;
-        } else {
-            const float Wn = logaddexp_f(Ws, w);
-            if (logf(uniform<float>(a.seed, (uint32_t)c, t, ROLE_LEAF, ((uint32_t)j << 16) | (uint32_t)nn)) <
-                w - Wn) {
-                WaveVec<EPL> th;
-                th.load(vec(eth), lane);
-                th.store(vec(V_THS), lane);
-                g.store(vec(V_GS), lane);
-                US = Un;
-            }
-            Ws = Wn;
-            WaveVec<EPL> rs;
-            rs.load(vec(V_RHOS), lane);
-#pragma unroll
-            for (int e = 0; e < EPL; ++e) rs.r[e] += p.r[e];
-            rs.store(vec(V_RHOS), lane);
-            for (int lev = 1; lev <= j; ++lev) {
-                if ((nn & ((1 << lev) - 1)) == 0) {
-                    WaveVec<EPL> ck;
-#pragma unroll
-                    for (int e = 0; e < EPL; ++e) ck.r[e] = rs.r[e] - p.r[e];
-                    p.store(vec(a.ckp0 + lev), lane);
-                    ck.store(vec(a.ckr0 + lev), lane);
-                }
-            }
-            for (int lev = 1; lev <= j; ++lev) {
-                if (((nn + 1) & ((1 << lev) - 1)) == 0) {
-                    WaveVec<EPL> ckp, span;
-                    ckp.load(vec(a.ckp0 + lev), lane);
-                    span.load(vec(a.ckr0 + lev), lane);
-#pragma unroll
-                    for (int e = 0; e < EPL; ++e) span.r[e] = rs.r[e] - span.r[e];
-                    if (wdot(ckp, span) <= 0.0f || wdot(p, span) <= 0.0f) fl |= NF_INVALID | NF_TURNED;
-                }
-            }
-            if (!(fl & NF_INVALID)) ++nn;
-        }
-        fl &= ~NF_PENDING;
-        k = (!(fl & NF_INVALID) && nn < (1 << j)) ? NS_INTEGRATE : NS_CHECK;
-    }
-
-    // 2) cheap states back to back until the next gradient request
-    for (int guard = 0; guard < 8; ++guard) {
-        if (k == NS_WAIT) {
-            if (!release) break;
-            k = NS_INIT;
-        }
-        if (k == NS_INIT) {
-            WaveVec<EPL> p0;
-#pragma unroll
-            for (int e = 0; e < EPL; ++e) {
-                const int d = e * 64 + lane;
-                p0.r[e] = d < a.D ? normal_at<float>(a.seed, (uint32_t)c, t, ROLE_MOM, 0, (uint32_t)d) : 0.0f;
-            }
-            H0 = UP + 0.5f * wdot(p0, p0);
-            p0.store(vec(V_PL), lane);
-            p0.store(vec(V_PR), lane);
-            p0.store(vec(V_RHO), lane);
-            WaveVec<EPL> th, g;
-            th.load(vec(V_THP), lane);
-            g.load(vec(V_GP), lane);
-            th.store(vec(V_THL), lane);
-            th.store(vec(V_THR), lane);
-            g.store(vec(V_GL), lane);
-            g.store(vec(V_GR), lane);
-            W = 0.0f;
-            j = 0;
-            fl = 0;
-            nleap = 0;
-            k = (j < a.J) ? NS_DOUBLE : NS_DONE;
-            continue;
-        }
-        if (k == NS_DOUBLE) {
-            v = uniform<float>(a.seed, (uint32_t)c, t, ROLE_DIR, (uint32_t)j) < 0.5f ? 1 : -1;
-            Ws = -INFINITY;
-            WaveVec<EPL> z;
-#pragma unroll
-            for (int e = 0; e < EPL; ++e) z.r[e] = 0.0f;
-            z.store(vec(V_RHOS), lane);
-            nn = 0;
-            fl &= ~NF_INVALID;
-            k = NS_INTEGRATE;
-            continue;
-        }
-        if (k == NS_INTEGRATE) {
-            if (budget <= 0) break;
-            const int eth = v > 0 ? V_THR : V_THL, ep = v > 0 ? V_PR : V_PL, eg = v > 0 ? V_GR : V_GL;
-            const float vhe = (float)v * he, veps = (float)v * a.eps;
-            WaveVec<EPL> th, p, g, ph;
-            th.load(vec(eth), lane);
-            p.load(vec(ep), lane);
-            g.load(vec(eg), lane);
-#pragma unroll
-            for (int e = 0; e < EPL; ++e) {
-                ph.r[e] = p.r[e] - vhe * g.r[e];
-                th.r[e] = th.r[e] + veps * ph.r[e];
-            }
-            ph.store(vec(V_PH), lane);
-            th.store(vec(eth), lane);
-            th.store(a.Thq + (size_t)c * a.Dp, lane);
-            fl |= NF_PENDING;
-            req = 1;
-            --budget;
-            ++steps;
-            break;
-        }
-        if (k == NS_CHECK) {
-            if (fl & NF_INVALID) {
-                fl |= NF_STOP;
-            } else {
-                if (logf(uniform<float>(a.seed, (uint32_t)c, t, ROLE_MERGE, (uint32_t)j)) < Ws - W) {
-                    WaveVec<EPL> th, g;
-                    th.load(vec(V_THS), lane);
-                    g.load(vec(V_GS), lane);
-                    th.store(vec(V_THP), lane);
-                    g.store(vec(V_GP), lane);
-                    UP = US;
-                }
-                W = logaddexp_f(W, Ws);
-                WaveVec<EPL> rho, rs, pl, pr;
-                rho.load(vec(V_RHO), lane);
-                rs.load(vec(V_RHOS), lane);
-#pragma unroll
-                for (int e = 0; e < EPL; ++e) rho.r[e] += rs.r[e];
-                rho.store(vec(V_RHO), lane);
-                pl.load(vec(V_PL), lane);
-                pr.load(vec(V_PR), lane);
-                if (wdot(pl, rho) <= 0.0f || wdot(pr, rho) <= 0.0f) fl |= NF_STOP | NF_TURNED;
-            }
-            ++j;
-            k = (!(fl & NF_STOP) && j < a.J) ? NS_DOUBLE : NS_DONE;
-            continue;
-        }
-        if (k == NS_DONE) {
-            WaveVec<EPL> th;
-            th.load(vec(V_THP), lane);
-            float* o = a.out + ((size_t)c * a.n + t) * a.D;
-#pragma unroll
-            for (int e = 0; e < EPL; ++e) {
-                const int d = e * 64 + lane;
-                if (d < a.D) o[d] = th.r[e];
-            }
-            if (lane == 0) a.counts[(size_t)c * a.n + t] = nleap;
-            ++t;
-            k = NS_INIT;
-            if (t >= a.tstop) break;
-            if (a.mode != 0) {
-                k = NS_WAIT;
-                break;
-            }
-            continue;
-        }
-        break;
-    }
-    if (lane == 0) {
-        a.t[c] = t;
-        a.k[c] = k;
-        a.jd[c] = j;
-        a.v[c] = v;
-        a.nn[c] = nn;
-        a.flags[c] = fl;
-        a.nleap[c] = nleap;
-        a.budget[c] = budget;
-        a.H0[c] = H0;
-        a.W[c] = W;
-        a.Ws[c] = Ws;
-        a.UP[c] = UP;
-        a.US[c] = US;
-        a.req[c] = req;
-        if (steps) atomicAdd(&a.ctr[0], steps);
-        if (t < a.tstop) {
-            atomicAdd(&a.wctr[3 + a.step % 3], 1u);
-            if (a.mode != 0 && k != NS_WAIT) atomicAdd(&a.wctr[a.step % 3], 1u);
-        }
-    }
+    nuts_chain_step<EPL>(a, c, lane);
 }
 
-// Chains that asked for a gradient, in chain order (one block).  In vmap mode
-// a gradient phase that anyone needs covers every chain.
 __global__ __launch_bounds__(1024) void nuts_compact_kernel(const int32_t* req, int m, int vmap, int32_t* list,
                                                             int32_t* count, unsigned long long* ctr)
 {
-    __shared__ int part[1024];
-    const int tid = threadIdx.x;
-    const int per = (m + 1023) / 1024;
-    const int b = tid * per, e = min(m, b + per);
-    int local = 0;
-    for (int i = b; i < e; ++i) local += req[i] != 0;
-    part[tid] = local;
-    __syncthreads();
-    // inclusive scan (Hillis-Steele)
-    for (int o = 1; o < 1024; o <<= 1) {
-        const int add = tid >= o ? part[tid - o] : 0;
-        __syncthreads();
-        part[tid] += add;
-        __syncthreads();
-    }
-    const int total = part[1023];
-    if (vmap) {
-        if (tid == 0) {
-            *count = total > 0 ? m : 0;
-            if (total > 0) atomicAdd(&ctr[1], (unsigned long long)(m - total));
-        }
-        if (total > 0)
-            for (int i = tid; i < m; i += 1024) list[i] = i;
-        return;
-    }
-    int pos = part[tid] - local;
-    for (int i = b; i < e; ++i)
-        if (req[i]) list[pos++] = i;
-    if (tid == 0) *count = total;
+    nuts_compact_block(req, m, vmap, list, count, ctr);
 }
 
 // Default start: theta0 ~ N(0, I) from the INIT stream (into both buffers).
@@ -331,47 +58,6 @@ __global__ void nuts_normal_init_kernel(float* thp, int vstride, float* thq, int
 }
 
 // ------------------------------------------------------------ host side
-static NutsK nuts_view(const JobDev& j, int mode, uint32_t step)
-{
-    NutsK a;
-    a.m = j.m;
-    a.n = j.n;
-    a.D = j.D;
-    a.Dp = j.Dp;
-    a.J = j.max_depth;
-    a.nvec = j.nvec;
-    a.ckp0 = V_FIXED - 1;  // level lev in [1, J] lives at ckp0 + lev
-    a.ckr0 = V_FIXED - 1 + j.max_depth;
-    a.mode = mode;
-    a.step = step;
-    a.tstop = j.tstop;
-    a.seed = j.seed;
-    a.eps = (float)j.step_size;
-    a.k = j.k;
-    a.jd = j.jd;
-    a.v = j.vdir;
-    a.nn = j.nn;
-    a.flags = j.flags;
-    a.nleap = j.evals;
-    a.t = j.t;
-    a.budget = j.budget;
-    a.H0 = (float*)j.H0;
-    a.W = (float*)j.Wsum;
-    a.Ws = (float*)j.Wsub;
-    a.UP = (float*)j.lx;
-    a.US = (float*)j.US;
-    a.V = (float*)j.V;
-    a.Thq = (float*)j.Thq;
-    a.Gres = (const float*)j.Gres;
-    a.Ures = (const float*)j.Ures;
-    a.req = j.req;
-    a.out = (float*)j.out;
-    a.counts = j.counts;
-    a.ctr = j.ctr;
-    a.wctr = j.wctr;
-    return a;
-}
-
 int nuts_nvec(int max_depth) { return V_FIXED + 2 * max_depth; }
 
 hipError_t nuts_init_state(const JobDev& j, const void* x0, hipStream_t s)

@@ -28,6 +28,8 @@ EXPORTS = [
     "fsmmc_chain_progress", "fsmmc_job_stats", "fsmmc_job_sync", "fsmmc_job_free",
     "fsmmc_last_error", "fsmmc_version", "fsmmc_eval_potential",
     "fsmmc_batch_create", "fsmmc_batch_run", "fsmmc_batch_stats", "fsmmc_batch_free",
+    "fsmmc_clock", "fsmmc_server_create", "fsmmc_server_submit", "fsmmc_server_poll",
+    "fsmmc_server_wait", "fsmmc_server_stats", "fsmmc_server_destroy",
 ]
 
 
@@ -61,7 +63,8 @@ class Stats(C.Structure):
 
 class BatchTune(C.Structure):
     _fields_ = [("autotune", C.c_int32), ("window", C.c_int32), ("dr_chunk", C.c_int32),
-                ("gemm_cols", C.c_int32), ("rounds_per_sync", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("gemm_cols", C.c_int32), ("rounds_per_sync", C.c_int32), ("nuts_steps", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class BatchCounters(C.Structure):
@@ -72,6 +75,25 @@ class BatchCounters(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("batch", BatchTune), ("ess_window", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class ServerDone(C.Structure):
+    _fields_ = [("job_id", C.c_uint64), ("status", C.c_int32), ("reserved", C.c_int32),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+class ServerCounters(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("failed", C.c_int64), ("rounds", C.c_int64), ("draws", C.c_int64),
+                ("live_jobs", C.c_int32), ("pending_jobs", C.c_int32), ("peak_live_jobs", C.c_int32),
+                ("reserved", C.c_int32), ("peak_bytes", C.c_uint64), ("gpu_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class FsmmcError(RuntimeError):
@@ -105,6 +127,13 @@ def _load():
         "fsmmc_batch_run": ([p, i64, p], C.c_int),
         "fsmmc_batch_stats": ([p, p], C.c_int),
         "fsmmc_batch_free": ([p], C.c_int),
+        "fsmmc_clock": ([], C.c_double),
+        "fsmmc_server_create": ([p, p, pp], C.c_int),
+        "fsmmc_server_submit": ([p, p, p, i32, i32, u64, p, p, p, C.POINTER(C.c_uint64)], C.c_int),
+        "fsmmc_server_poll": ([p, p, i32, C.POINTER(C.c_int32)], C.c_int),
+        "fsmmc_server_wait": ([p, C.c_double, p], C.c_int),
+        "fsmmc_server_stats": ([p, p], C.c_int),
+        "fsmmc_server_destroy": ([p], C.c_int),
         "fsmmc_last_error": ([], C.c_char_p),
         "fsmmc_version": ([], C.c_char_p),
     }
@@ -356,9 +385,9 @@ class Batch:
     """Several jobs stepped together (one graph replay per round)."""
 
     def __init__(self, ctx, jobs, stream=None, autotune=False, window=0, dr_chunk=0, gemm_cols=0,
-                 rounds_per_sync=0):
+                 rounds_per_sync=0, nuts_steps=0):
         self.jobs = list(jobs)
-        tune = BatchTune(1 if autotune else 0, window, dr_chunk, gemm_cols, rounds_per_sync)
+        tune = BatchTune(1 if autotune else 0, window, dr_chunk, gemm_cols, rounds_per_sync, nuts_steps)
         self.handle = fsmmc_batch_create(ctx.handle, [j.handle for j in self.jobs], stream, tune)
 
     def run(self, max_rounds=0):
@@ -371,3 +400,62 @@ class Batch:
         if self.handle is not None:
             fsmmc_batch_free(self.handle)
             self.handle = None
+
+
+def clock():
+    """The monotonic host clock (seconds) the server stamps its records with."""
+    return lib.fsmmc_clock()
+
+
+class Server:
+    """Continuous-batching server: jobs submitted at any time are admitted
+    under the context's HBM budget, stepped together and retired as they
+    finish.  Device buffers handed to submit() are kept alive here until the
+    job is reported by poll()."""
+
+    def __init__(self, ctx, ess_window=0, nuts_steps=0, rounds_per_sync=0, window=0, dr_chunk=0,
+                 gemm_cols=0):
+        cfg = ServerConfig(BatchTune(0, window, dr_chunk, gemm_cols, rounds_per_sync, nuts_steps), ess_window)
+        out = C.c_void_p()
+        _check(lib.fsmmc_server_create(ctx.handle, C.byref(cfg), C.byref(out)))
+        self.handle = out
+        self._keep = {}
+
+    def submit(self, target, sampler, n_chains, n_draws, seed, out, x0=None, counts=None):
+        spec, keep = target
+        x0 = _dense(x0)
+        if not out.is_contiguous() or (counts is not None and not counts.is_contiguous()):
+            raise ValueError("out and counts must be contiguous device tensors")
+        jid = C.c_uint64()
+        _check(lib.fsmmc_server_submit(self.handle, C.byref(spec), C.byref(sampler), n_chains, n_draws, seed,
+                                       _ptr(x0), _ptr(out), _ptr(counts), C.byref(jid)))
+        self._keep[jid.value] = (keep, x0, out, counts)
+        return jid.value
+
+    def poll(self, cap=1024):
+        buf = (ServerDone * cap)()
+        n = C.c_int32()
+        _check(lib.fsmmc_server_poll(self.handle, buf, cap, C.byref(n)))
+        recs = []
+        for i in range(n.value):
+            r = buf[i]
+            self._keep.pop(r.job_id, None)
+            recs.append(dict(job_id=r.job_id, status=r.status, t_submit=r.t_submit, t_admit=r.t_admit,
+                             t_done=r.t_done))
+        return recs
+
+    def wait(self, timeout=-1.0):
+        idle = C.c_int32()
+        _check(lib.fsmmc_server_wait(self.handle, float(timeout), C.byref(idle)))
+        return bool(idle.value)
+
+    def stats(self):
+        s = ServerCounters()
+        _check(lib.fsmmc_server_stats(self.handle, C.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if self.handle is not None:
+            _check(lib.fsmmc_server_destroy(self.handle))
+            self.handle = None
+            self._keep.clear()

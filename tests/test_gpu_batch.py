@@ -124,6 +124,37 @@ def test_batch_round_by_round_and_mid_draw_start(F, ctx, reference):
     assert_same(got, reference)
 
 
+NUTS_MIX = [(700, 20, 30, 30, 31, 502, 0.05), (1500, 90, 20, 25, 32, 505, 0.03)]
+
+
+def nuts_jobs(F, ctx, mix):
+    jobs = []
+    for N, D, m, n, ds, cs, eps in mix:
+        w = inputs.logreg(n_data=N, dim=D, seed=ds)
+        x0 = inputs.logreg_laplace(w["X"], w["y"], m, seed=ds + 7)["x0"]
+        jobs.append(F.Job(ctx, F.logreg_target(_dev(w["X"]), _dev(w["y"])), F.nuts_sampler(eps), m, n, cs,
+                          x0=_dev(x0)))
+    return jobs
+
+
+def test_batch_with_nuts_jobs(F, ctx, reference):
+    ref_n = []
+    for j in nuts_jobs(F, ctx, NUTS_MIX):
+        while not j.step_fsm(0):
+            pass
+        ref_n.append((j.samples(), j.counts()))
+        j.free()
+    jobs = make_jobs(F, ctx) + nuts_jobs(F, ctx, NUTS_MIX)
+    try:
+        b = F.Batch(ctx, jobs, window=8, dr_chunk=8, nuts_steps=5, autotune=True)
+        assert b.run(0)
+        b.free()
+        assert_same(results(jobs), reference + ref_n)
+    finally:
+        for j in jobs:
+            j.free()
+
+
 def test_batch_wide_drmh(F, ctx):
     mix = [("gauss", 16, 64, 20, 301), ("funnel", 13, 100, 30, 302)]
     ref = alone(F, ctx, ess_mix=ESS_MIX[:2], dr_mix=mix)
@@ -133,12 +164,12 @@ def test_batch_wide_drmh(F, ctx):
 
 def test_batch_ownership_and_errors(F, ctx):
     jobs = make_jobs(F, ctx, ESS_MIX[:1], DR_MIX[:1])
-    X = torch.randn(64, 5, device="cuda")
-    yl = (torch.rand(64, device="cuda") < 0.5).float()
-    nuts = F.Job(ctx, F.logreg_target(X, yl), F.nuts_sampler(0.1), 4, 4, 1)
+    w = inputs.gp_gauss(dim=16)
+    f64 = F.Job(ctx, F.gp_target(torch.tensor(w["L"], device="cuda"), torch.tensor(w["y"], device="cuda"),
+                                 noise_sd=0.1), F.ess_sampler(F.F64), 4, 4, 1)
     try:
         with pytest.raises(F.FsmmcError) as e:
-            F.Batch(ctx, [jobs[0], nuts])
+            F.Batch(ctx, [jobs[0], f64])
         assert e.value.status == F.ENOTSUP
         with pytest.raises(F.FsmmcError) as e:
             F.Batch(ctx, [jobs[0], jobs[0]])
@@ -165,7 +196,7 @@ def test_batch_ownership_and_errors(F, ctx):
                 pass
         assert_same(results(jobs), alone(F, ctx, ESS_MIX[:1], DR_MIX[:1]))
     finally:
-        nuts.free()
+        f64.free()
         for j in jobs:
             j.free()
 

@@ -149,6 +149,24 @@ def test_ess_explicit_x0(F, ctx):
     assert err <= 1e-4 and (flips >= 0).sum() == 0
 
 
+@pytest.mark.parametrize("fp64", [True, False])
+def test_ess_pipelined_windows_equal_sequential(F, ctx, fp64):
+    # step_fsm(0) overlaps the next window's ellipse GEMM with the current
+    # window; a finite budget takes the sequential path.  Many small windows.
+    w = inputs.gp_gauss(dim=40, lengthscale=0.2, jitter=1e-6, noise_sd=0.1, seed=77) if fp64 else \
+        inputs.gp_logistic(dim=200, lengthscale=0.05, jitter=1e-5, seed=78)
+    noise = 0.1 if fp64 else None
+    a = gpu_ess(F, ctx, w, 33, 61, 9, fp64=fp64, noise_sd=noise, window=4)
+    b = gpu_ess(F, ctx, w, 33, 61, 9, fp64=fp64, noise_sd=noise, window=4, max_steps=10 ** 9)
+    c = gpu_ess(F, ctx, w, 33, 61, 9, fp64=fp64, noise_sd=noise, window=4, runtime="compact")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+    # draws use distinct ellipse directions: no two draws of a chain repeat a proposal step
+    R, RC, _ = oracle_ess(w, 4, 61, 9, noise_sd=noise)
+    err, flips = parity.compare_draws(a[0][:4], R, a[1][:4], RC, first=61)
+    assert err <= (1e-10 if fp64 else 1e-4)
+
+
 def test_ess_step_budget_semantics(F, ctx):
     w = inputs.gp_logistic(dim=128, lengthscale=0.1, seed=5)
     L, y = _dev(w["L"], torch.float32), _dev(w["y"], torch.float32)

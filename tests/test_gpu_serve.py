@@ -1,0 +1,189 @@
+"""GPU tests of the continuous-batching server.
+
+* Each served job's draws and loop counts equal, bit for bit, the same job
+  run alone with step_fsm, whatever else is in the mix and whenever it
+  arrives.
+* Admission respects the context's HBM budget; a job that cannot fit even
+  alone fails with EBUDGET; short jobs retire while a long one keeps running.
+"""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2503_17405_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2503_17405_amd import fsmmc
+    return fsmmc
+
+
+def _dev(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda")
+
+
+# ("ess", dim, chains, draws, data seed, chain seed) / ("dr", target, dim, chains, draws, seed) /
+# ("nuts", rows, dim, chains, draws, data seed, chain seed, step)
+MIX = [("ess", 300, 24, 40, 21, 501), ("nuts", 700, 20, 32, 30, 31, 502, 0.05),
+       ("dr", "funnel", 10, 500, 60, 503), ("ess", 64, 50, 80, 22, 504),
+       ("nuts", 1500, 90, 20, 25, 32, 505, 0.03), ("dr", "gauss", 5, 130, 45, 506),
+       ("ess", 1000, 6, 15, 23, 507), ("nuts", 513, 64, 40, 12, 33, 508, 0.05)]
+
+
+def build(F, spec):
+    """(target, sampler, m, n, seed, x0, dim) of one mix entry."""
+    if spec[0] == "ess":
+        _, D, m, n, ds, cs = spec
+        w = inputs.gp_logistic(dim=D, lengthscale=0.05, jitter=1e-5, seed=ds)
+        return F.gp_target(_dev(w["L"]), _dev(w["y"])), F.ess_sampler(), m, n, cs, None, D
+    if spec[0] == "dr":
+        _, kind, D, m, n, seed = spec
+        tgt = F.funnel_target(D) if kind == "funnel" else F.gauss_target(torch.linspace(0.5, 2.0, D, device="cuda"))
+        return tgt, F.dr_sampler(), m, n, seed, None, D
+    _, N, D, m, n, ds, cs, eps = spec
+    w = inputs.logreg(n_data=N, dim=D, seed=ds)
+    x0 = inputs.logreg_laplace(w["X"], w["y"], m, seed=ds + 7)["x0"]
+    return (F.logreg_target(_dev(w["X"]), _dev(w["y"])), F.nuts_sampler(eps), m, n, cs,
+            _dev(x0), D)
+
+
+def alone(F, ctx, spec):
+    tgt, smp, m, n, seed, x0, D = build(F, spec)
+    job = F.Job(ctx, tgt, smp, m, n, seed, x0=x0)
+    try:
+        while not job.step_fsm(0):
+            pass
+        return job.samples(), job.counts()
+    finally:
+        job.free()
+
+
+def serve(F, ctx, specs, gaps=None, **cfg):
+    srv = F.Server(ctx, **cfg)
+    outs, ids = [], []
+    try:
+        for k, spec in enumerate(specs):
+            tgt, smp, m, n, seed, x0, D = build(F, spec)
+            out = torch.empty((m, n, D), dtype=torch.float32, device="cuda")
+            cnt = torch.empty((m, n), dtype=torch.int32, device="cuda")
+            ids.append(srv.submit(tgt, smp, m, n, seed, out, x0=x0, counts=cnt))
+            outs.append((out, cnt))
+            if gaps:
+                time.sleep(gaps[k % len(gaps)])
+        assert srv.wait(600.0)
+        recs = {r["job_id"]: r for r in srv.poll()}
+        st = srv.stats()
+    finally:
+        srv.close()
+    res = [(o.cpu().numpy(), c.cpu().numpy()) for o, c in outs]
+    return res, [recs[i] for i in ids], st
+
+
+@pytest.fixture(scope="module")
+def reference(F):
+    ctx = F.Context(0)
+    try:
+        yield [alone(F, ctx, s) for s in MIX]
+    finally:
+        ctx.close()
+
+
+def test_served_mix_equals_alone(F, reference):
+    ctx = F.Context(0)
+    try:
+        got, recs, st = serve(F, ctx, MIX, gaps=[0.0, 0.02, 0.0, 0.05])
+    finally:
+        ctx.close()
+    for k, ((S, C), (R, RC)) in enumerate(zip(got, reference)):
+        assert recs[k]["status"] == F.OK
+        assert np.array_equal(C, RC), "job %d counts" % k
+        assert np.array_equal(S, R), "job %d draws" % k
+        assert recs[k]["t_submit"] <= recs[k]["t_admit"] <= recs[k]["t_done"]
+    assert st["completed"] == len(MIX) and st["failed"] == 0 and st["live_jobs"] == 0
+    print("served %d jobs: %d rounds, %.1f ms on device, peak %d live jobs"
+          % (len(MIX), st["rounds"], st["gpu_ms"], st["peak_live_jobs"]))
+
+
+def test_served_under_budget_and_oversized_job(F, reference):
+    # budget: room for the largest single job's state plus a little
+    probe = F.Context(0)
+    sizes = []
+    for spec in MIX:
+        tgt, smp, m, n, seed, x0, D = build(F, spec)
+        j = F.Job(probe, tgt, smp, m, n, seed, x0=x0, window=16,
+                  out=torch.empty((m, n, D), dtype=torch.float32, device="cuda"))
+        sizes.append(probe.bytes_in_use())
+        j.free()
+    probe.close()
+    budget = int(max(sizes) * 1.2)
+    ctx = F.Context(0, hbm_budget_bytes=budget)
+    try:
+        got, recs, st = serve(F, ctx, MIX, nuts_steps=8, rounds_per_sync=2)
+        assert st["peak_bytes"] <= budget
+        assert st["peak_live_jobs"] < len(MIX)
+        for k, ((S, C), (R, RC)) in enumerate(zip(got, reference)):
+            assert recs[k]["status"] == F.OK
+            assert np.array_equal(C, RC) and np.array_equal(S, R), "job %d" % k
+        # a job whose state alone exceeds the budget fails with EBUDGET, others proceed
+        big = ("ess", 1000, 4096, 100, 24, 509)
+        srv = F.Server(ctx)
+        try:
+            tgt, smp, m, n, seed, x0, D = build(F, big)
+            out = torch.empty((m, n, D), dtype=torch.float32, device="cuda")
+            jb = srv.submit(tgt, smp, m, n, seed, out)
+            tgt2, smp2, m2, n2, seed2, x02, D2 = build(F, MIX[3])
+            out2 = torch.empty((m2, n2, D2), dtype=torch.float32, device="cuda")
+            j2 = srv.submit(tgt2, smp2, m2, n2, seed2, out2)
+            assert srv.wait(120.0)
+            recs = {r["job_id"]: r for r in srv.poll()}
+            assert recs[jb]["status"] == F.EBUDGET
+            assert recs[j2]["status"] == F.OK
+            assert np.array_equal(out2.cpu().numpy(), reference[3][0])
+        finally:
+            srv.close()
+    finally:
+        ctx.close()
+
+
+def test_short_jobs_retire_while_a_long_job_runs(F):
+    ctx = F.Context(0)
+    try:
+        long_job = ("dr", "funnel", 10, 4096, 4000, 601)
+        short = [("dr", "gauss", 3, 64, 10, 602 + k) for k in range(4)]
+        _, recs, st = serve(F, ctx, [long_job] + short, dr_chunk=8)
+        t_long = recs[0]["t_done"]
+        assert all(r["status"] == F.OK for r in recs)
+        assert all(r["t_done"] < t_long for r in recs[1:])
+    finally:
+        ctx.close()
+
+
+def test_server_argument_errors(F):
+    ctx = F.Context(0)
+    srv = F.Server(ctx)
+    try:
+        tgt, smp, m, n, seed, x0, D = build(F, MIX[3])
+        assert F.lib.fsmmc_server_submit(srv.handle, None, None, 1, 1, 0, None, None, None, None) == F.EINVAL
+        out = torch.empty((m, n, D), dtype=torch.float32, device="cuda")
+        spec, keep = tgt
+        jid = F.C.c_uint64()
+        st = F.lib.fsmmc_server_submit(srv.handle, F.C.byref(spec), F.C.byref(smp), m, n, seed, None, None,
+                                       None, F.C.byref(jid))
+        assert st == F.EINVAL  # no output buffer
+        smp64 = F.ess_sampler(F.F64)
+        st = F.lib.fsmmc_server_submit(srv.handle, F.C.byref(spec), F.C.byref(smp64), m, n, seed, None,
+                                       F._ptr(out), None, F.C.byref(jid))
+        assert st == F.ENOTSUP
+        st = F.lib.fsmmc_server_submit(srv.handle, F.C.byref(spec), F.C.byref(smp), 0, n, seed, None,
+                                       F._ptr(out), None, F.C.byref(jid))
+        assert st == F.EINVAL
+        assert srv.wait(1.0)
+        assert srv.stats()["submitted"] == 0
+    finally:
+        srv.close()
+        ctx.close()
