@@ -28,8 +28,10 @@ Reported beside it, on the same box and run:
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -38,6 +40,23 @@ sys.path.insert(0, ROOT)
 
 METRIC = "draws/sec FSM vs synchronized (ESS, NUTS, 8192 chains); p50/p99 job latency"
 PEAK_MFMA_F32 = 157.3  # TFLOP/s, MI355X dense FP32 MFMA
+
+
+def stored_traffic():
+    """HBM bytes per full-window launch of the ellipse GEMM, from the committed rocprofv3
+    counter summary -- None if the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "nu_gemm_d1024_traffic.md")
+    src = os.path.join(ROOT, "paper_2503_17405_amd", "csrc", "ess_device.h")
+    try:
+        txt = open(path).read()
+        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m1 = re.search(r"traffic_bytes_per_launch: (\d+)", txt)
+    m2 = re.search(r"source_sha256 \(.*?\): ([0-9a-f]{64})", txt)
+    if not (m1 and m2) or m2.group(1) != cur:
+        return None
+    return int(m1.group(1))
 
 
 def log(*a):
@@ -99,8 +118,22 @@ def bench_ess(F, ctx, args):
                R_hat_m=Dg.r_hat_m(counts, m))
     g_ms, g_n = st["kernel_ms"][0], st["kernel_launches"][0]
     flops = float(m) * n * D * (D + 1)
+    # in the job, each window's GEMM shares the chip with the previous window's FSM kernel
     res["gemm"] = dict(kernel="nu_gemm_mfma_kernel<4>", ms=g_ms, launches=g_n, avg_us=1e3 * g_ms / max(g_n, 1),
-                       tflops=flops / (g_ms * 1e-3) / 1e12, flop_per_column=D * (D + 1))
+                       tflops=flops / (g_ms * 1e-3) / 1e12, flop_per_column=D * (D + 1),
+                       flop_per_launch=flops / max(g_n, 1))
+    # the same job with a finite step budget runs its windows one after another:
+    # the GEMM launches then have the chip to themselves
+    log("ESS FSM, windows not overlapped")
+    job = make()
+    while not job.step_fsm(1 << 40):
+        pass
+    si = job.stats()
+    job.free()
+    gi_ms, gi_n = si["kernel_ms"][0], si["kernel_launches"][0]
+    res["gemm_isolated"] = dict(ms=gi_ms, launches=gi_n, avg_us=1e3 * gi_ms / max(gi_n, 1),
+                                tflops=flops / (gi_ms * 1e-3) / 1e12,
+                                bit_exact_vs_fsm=bool(checksum(out) == ref))
     sync = {}
     if not args.no_sync:
         for name, mode in (("vmap", F.SYNC_VMAP), ("compact", F.SYNC_COMPACT)):
@@ -294,7 +327,11 @@ def bench_serve(F, args):
             time.sleep(min(0.002, max(0.0, js["t"] - (F.clock() - start))))
         tgt, smp, x0 = data[k]
         ids.append(srv.submit(tgt, smp, js["m"], js["n"], js["seed"], outs[k], x0=x0))
-    srv.wait(-1.0)
+    log("  all %d jobs submitted after %.2f s" % (len(stream), F.clock() - start))
+    while not srv.wait(10.0):
+        st = srv.stats()
+        log("  server: %d/%d done, %d live, %d pending, %.1f s" % (st["completed"], len(stream), st["live_jobs"],
+                                                                  st["pending_jobs"], F.clock() - start))
     recs = {r["job_id"]: r for r in srv.poll(len(stream) + 8)}
     sst = srv.stats()
     srv.close()
@@ -302,6 +339,8 @@ def bench_serve(F, args):
     ok = all(recs[i]["status"] == F.OK for i in ids)
     lat_srv = [recs[i]["t_done"] - recs[i]["t_submit"] for i in ids]
     span_srv = max(recs[i]["t_done"] for i in ids) - start
+    log("  server: span %.2f s, p50 %.2f s, p99 %.2f s" % (span_srv, np.percentile(lat_srv, 50),
+                                                        np.percentile(lat_srv, 99)))
     sums = [checksum(o) for o in outs]
 
     log("C5 one job at a time")
@@ -319,6 +358,7 @@ def bench_serve(F, args):
         j.free()
         t_done = F.clock() - start
         lat_one.append(t_done - js["t"])
+        log("  job %d (%s m=%d n=%d D=%d): done at %.2f s" % (k, js["kind"], js["m"], js["n"], js["D"], t_done))
     ctx.close()
     same = all(checksum(o) == s for o, s in zip(outs, sums))
     del outs
@@ -368,8 +408,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--funnel-chains", type=int, default=65536)
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-jobs", type=int, default=120)
+    ap.add_argument("--serve-jobs", type=int, default=40)
     ap.add_argument("--serve-budget-gib", type=int, default=64)
+    ap.add_argument("--calib-copy-gib", type=int, default=0,
+                    help="also run a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -380,6 +422,16 @@ def main():
     import torch
 
     from paper_2503_17405_amd import fsmmc as F
+
+    if args.calib_copy_gib > 0:
+        a = torch.empty(args.calib_copy_gib << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: %d GiB read, %d GiB written" % (args.calib_copy_gib, args.calib_copy_gib))
+        del a, b
+        torch.cuda.empty_cache()
 
     ctx = F.Context(0)
     ess, w, seed = bench_ess(F, ctx, args)
@@ -427,7 +479,12 @@ def main():
                    "chains": args.chains, "draws": args.draws, "dim": 1024},
         "roofline": {"bound": "mfma", "kernel": g["kernel"], "achieved": g["tflops"],
                      "peak": PEAK_MFMA_F32, "unit": "TFLOP/s", "frac": g["tflops"] / PEAK_MFMA_F32,
-                     "traffic": None, "avg_launch_us": g["avg_us"], "launches": g["launches"]},
+                     "traffic": stored_traffic(), "avg_launch_us": g["avg_us"], "launches": g["launches"],
+                     "flop_per_launch": g["flop_per_launch"],
+                     "note": "in the job, each window's GEMM overlaps the previous window's FSM kernel",
+                     "isolated": {"achieved": ess["gemm_isolated"]["tflops"],
+                                  "frac": ess["gemm_isolated"]["tflops"] / PEAK_MFMA_F32,
+                                  "avg_launch_us": ess["gemm_isolated"]["avg_us"]}},
         "ess": ess,
         "speedup_vs_sync_vmap": ess["sync"].get("vmap", {}).get("speedup_fsm"),
         "speedup_vs_sync_compact": ess["sync"].get("compact", {}).get("speedup_fsm"),
