@@ -8,12 +8,11 @@
 
 namespace fsmmc {
 
-
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 struct GradK {
-    int m, N, Dp, slice_rows, nslices, dense;  // dense > 0: columns are chains 0 .. dense-1
+    int m, N, D, Dp, slice_rows, nslices, dense;  // dense > 0: columns are chains 0 .. dense-1
     const float* X;   // Np x Dp, zero padded
     const float* y;   // Np
     const float* Th;  // m x Dp, indexed by chain
@@ -24,14 +23,16 @@ struct GradK {
 };
 
 // One block (4 waves): listed chains 64 ct .. 64 ct + 63, row slice sl.
-template <int DT>
+// NK8 > 0: the dimension rounded up to 8 is 8 NK8 (compile-time trip counts,
+// fully unrolled); NK8 = 0: any dimension up to 32 DT (run-time trip counts).
+template <int DT, int NK8 = 0>
 __device__ __forceinline__ void logreg_grad_tile(const GradK& a, int ct, int sl)
 {
-
-    constexpr int DP = 32 * DT;   // padded dimension
-    constexpr int TP = DP + 4;    // LDS row pitch of Theta and X chunks
-    constexpr int RP = 64 + 4;    // LDS row pitch of r
-    constexpr int GT = DT / 2;    // 32 x 32 gradient tiles per wave
+    static_assert(NK8 >= 0 && 8 * NK8 <= 32 * DT, "dimension class exceeds the tile");
+    constexpr int DP = 32 * DT;  // padded dimension (row pitch of X and Theta in HBM)
+    constexpr int TP = DP + 4;   // LDS row pitch of Theta and X chunks (conflict-free eta reads)
+    constexpr int RP = 64 + 16;  // LDS row pitch of r (conflict-free gradient reads)
+    constexpr int NT = DP / 16;  // gradient d tiles of 16 (at most)
     __shared__ float Ths[64 * TP];
     __shared__ float Xs[2][32 * TP];
     __shared__ float Rs[32 * RP];
@@ -41,7 +42,10 @@ __device__ __forceinline__ void logreg_grad_tile(const GradK& a, int ct, int sl)
     const int ncols = a.dense > 0 ? a.dense : *a.count;
     if (ct * 64 >= ncols) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int l16 = lane & 15, q4 = lane >> 4, l32 = lane & 31, h = lane >> 5;
+    const int l16 = lane & 15, q4 = lane >> 4;
+    // K steps of 4 for eta, 16-row tiles of the gradient
+    const int nk4 = NK8 > 0 ? 2 * NK8 : (a.D + 3) >> 2;
+    const int nt16 = NK8 > 0 ? (NK8 + 1) / 2 : (a.D + 15) >> 4;
 
     if (tid < 64) {
         const int g = ct * 64 + tid;
@@ -53,22 +57,20 @@ __device__ __forceinline__ void logreg_grad_tile(const GradK& a, int ct, int sl)
         const int ch = cols[col];
         Ths[col * TP + d] = ch >= 0 ? a.Th[(size_t)ch * DP + d] : 0.0f;
     }
-
-    // roles
-    const int rt = wave & 1;          // eta row tile (16 rows)
-    const int et0 = 2 * (wave >> 1);  // eta chain tiles et0, et0 + 1 (16 chains each)
-    // gradient tiles (32 x 32): tile id = wave * GT + t, d tile id >> 1, chain tile id & 1
-    floatx16 accg[GT];
+    // roles: eta rows 16 rt .. +15 x chain tiles et0, et0 + 1; gradient: chain tile `wave`, every d tile
+    const int rt = wave & 1;
+    const int et0 = 2 * (wave >> 1);
+    floatx4 accg[NT];
 #pragma unroll
-    for (int t = 0; t < GT; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int q = 0; q < 16; ++q) accg[t][q] = 0.0f;
+        for (int q = 0; q < 4; ++q) accg[t][q] = 0.0f;
     float uacc[2] = {0.0f, 0.0f};
 
     const int rb = sl * a.slice_rows;
     const int re = min(rb + a.slice_rows, a.N);
     const int nchunk = (re - rb + 31) / 32;
-    constexpr int V4 = 32 * DP / 4 / 256;  // float4 per thread per chunk
+    constexpr int V4 = 32 * DP / 4 / 256;
     floatx4 stage[V4];
     if (nchunk > 0) {
         const floatx4* src = reinterpret_cast<const floatx4*>(a.X + (size_t)rb * DP);
@@ -87,10 +89,10 @@ __device__ __forceinline__ void logreg_grad_tile(const GradK& a, int ct, int sl)
         }
         __syncthreads();  // chunk ch in Xs[buf]; previous chunk's Rs and Xs[buf ^ 1] no longer read
         const float* X = Xs[buf];
-        // 1. eta tiles (16 x 16), K = DP in steps of 4
+        // 1. eta tiles (16 rows x 16 chains), K = D rounded up to 4
         floatx4 e0 = {0.0f, 0.0f, 0.0f, 0.0f}, e1 = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll 8
-        for (int kk = 0; kk < DP / 4; ++kk) {
+        for (int kk = 0; kk < nk4; ++kk) {
             const int k = 4 * kk + q4;
             const float xa = X[(16 * rt + l16) * TP + k];
             const float b0 = Ths[(16 * et0 + l16) * TP + k];
@@ -98,15 +100,17 @@ __device__ __forceinline__ void logreg_grad_tile(const GradK& a, int ct, int sl)
             e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa, b0, e0, 0, 0, 0);
             e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa, b1, e1, 0, 0, 0);
         }
-        // 2. r and the log-likelihood (lane: chain 16 et + l16, rows 4 q4 .. +3)
+        // 2. r = y - sigmoid(eta) into LDS, and the log-likelihood: sum [y eta - max(eta, 0)]
+        //    minus one log of the product of the four factors 1 + e^-|eta| (each in (1, 2])
         const int r0 = rb + 32 * ch;
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             const floatx4 e = t ? e1 : e0;
             const int col = 16 * (et0 + t) + l16;
+            float lin = 0.0f, prod = 1.0f;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int lr = 16 * rt + 4 * q4 + i;  // row within the chunk
+                const int lr = 16 * rt + 4 * q4 + i;
                 const int row = r0 + lr;
                 const bool ok = row < re;
                 const float v = e[i];
@@ -114,21 +118,25 @@ __device__ __forceinline__ void logreg_grad_tile(const GradK& a, int ct, int sl)
                 const float ex = __expf(-fabsf(v));
                 const float inv = __frcp_rn(1.0f + ex);
                 const float sig = v >= 0.0f ? inv : ex * inv;
-                const float sp = fmaxf(v, 0.0f) + __logf(1.0f + ex);
-                uacc[t] += ok ? (yv * v - sp) : 0.0f;
+                lin += ok ? (yv * v - fmaxf(v, 0.0f)) : 0.0f;
+                prod *= ok ? 1.0f + ex : 1.0f;
                 Rs[lr * RP + col] = ok ? (yv - sig) : 0.0f;
             }
+            uacc[t] += lin - __logf(prod);
         }
         __syncthreads();  // r complete
-        // 3. gradient tiles, K = 32 rows in steps of 2
-#pragma unroll 4
-        for (int kk = 0; kk < 16; ++kk) {
-            const int row = 2 * kk + h;
+        // 3. X_chunk^T r: 16 d x 16 chains tiles, K = 32 rows in steps of 4
+        float rv[8];
 #pragma unroll
-            for (int t = 0; t < GT; ++t) {
-                const float xa = X[row * TP + 32 * ((wave * GT + t) >> 1) + l32];
-                const float rb_ = Rs[row * RP + 32 * ((wave * GT + t) & 1) + l32];
-                accg[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(xa, rb_, accg[t], 0, 0, 0);
+        for (int kk = 0; kk < 8; ++kk) rv[kk] = Rs[(4 * kk + q4) * RP + 16 * wave + l16];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            if (t < nt16) {
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) {
+                    const float xa = X[(4 * kk + q4) * TP + 16 * t + l16];
+                    accg[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa, rv[kk], accg[t], 0, 0, 0);
+                }
             }
         }
         if (ch + 1 < nchunk) {
@@ -145,20 +153,19 @@ __device__ __forceinline__ void logreg_grad_tile(const GradK& a, int ct, int sl)
         uacc[t] += __shfl_xor(uacc[t], 16, 64);
         uacc[t] += __shfl_xor(uacc[t], 32, 64);
     }
-    __syncthreads();  // all waves done with Xs / Rs
+    __syncthreads();
     if (q4 == 0) {
         Ured[wave][16 * et0 + l16] = uacc[0];
         Ured[wave][16 * (et0 + 1) + l16] = uacc[1];
     }
-    // gradient tiles -> LDS [d][chain] (reusing Ths) for coalesced stores
+    // gradient tiles -> LDS [chain][d] (reusing Ths) for coalesced stores
     float* Red = Ths;
 #pragma unroll
-    for (int t = 0; t < GT; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int d = 32 * ((wave * GT + t) >> 1) + 8 * (q >> 2) + 4 * h + (q & 3);
-            const int col = 32 * ((wave * GT + t) & 1) + l32;
-            Red[col * TP + d] = accg[t][q];
+        for (int q = 0; q < 4; ++q) {
+            const int d = 16 * t + 4 * q4 + q;
+            Red[(16 * wave + l16) * TP + d] = t < nt16 ? accg[t][q] : 0.0f;
         }
     __syncthreads();
     for (int i = tid; i < 64 * DP; i += 256) {
@@ -172,6 +179,8 @@ __device__ __forceinline__ void logreg_grad_tile(const GradK& a, int ct, int sl)
         a.Upart[(size_t)sl * a.m + cols[tid]] = Ured[w0][tid] + Ured[w0 + 1][tid];
     }
 }
+
+// v2: eta on 16x16x4 with K = ceil(D/4)*4; X^T r on 16x16x4 tiles of 16 d; one log per 4 rows
 
 struct ReduceK {
     int m, Dp, nslices, dense;
@@ -218,6 +227,7 @@ inline GradK grad_view(const JobDev& j, int dense)
     GradK g;
     g.m = j.m;
     g.N = j.N;
+    g.D = j.D;
     g.Dp = j.Dp;
     g.slice_rows = j.slice_rows;
     g.nslices = j.nslices;
