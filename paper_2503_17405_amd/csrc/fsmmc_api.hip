@@ -432,10 +432,15 @@ static fsmmc_status nuts_run(fsmmc_job* job, int mode, int64_t max_steps, uint32
         HIP_TRY(hipMemcpyAsync(h + 6, d.count, 4, hipMemcpyDeviceToHost, job->stream));
         HIP_TRY(hipStreamSynchronize(job->stream));
         harvest(job);
-        alive = h[3 + (job->step - 1) % 3];
         const uint32_t reqs = h[6];
+        if (mode == 0) {
+            // FSM: a chain short of tstop requests a gradient every step unless its
+            // budget is spent, so no request means every chain is done or out of budget
+            if (reqs == 0) break;
+            continue;
+        }
+        alive = h[3 + (job->step - 1) % 3];
         if (alive == 0) break;
-        if (mode == 0 && reqs == 0) break;  // every live chain has spent its budget
     }
     if (all_done) {
         std::vector<uint32_t> t(d.m);

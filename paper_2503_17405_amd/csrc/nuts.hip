@@ -36,8 +36,25 @@ __global__ __launch_bounds__(256) void nuts_step_kernel(NutsK a)
         a.wctr[(a.step + 1) % 3] = 0u;
         a.wctr[3 + (a.step + 1) % 3] = 0u;
     }
-    if (c >= a.m) return;
-    nuts_chain_step<EPL>(a, c, lane);
+    int bits = 0;
+    if (c < a.m) bits = nuts_chain_step<EPL>(a, c, lane);
+    if (a.mode == 0) return;  // the FSM runtime stops when no chain requests a gradient
+    // synchronized runtimes: chains alive / still inside their draw, one atomic per block
+    __shared__ unsigned s_alive, s_indraw;
+    if (threadIdx.x == 0) {
+        s_alive = 0;
+        s_indraw = 0;
+    }
+    __syncthreads();
+    if (lane == 0 && bits) {
+        atomicAdd(&s_alive, (bits & NC_ALIVE) ? 1u : 0u);
+        atomicAdd(&s_indraw, (bits & NC_INDRAW) ? 1u : 0u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_alive) atomicAdd(&a.wctr[3 + a.step % 3], s_alive);
+        if (s_indraw) atomicAdd(&a.wctr[a.step % 3], s_indraw);
+    }
 }
 
 __global__ __launch_bounds__(1024) void nuts_compact_kernel(const int32_t* req, int m, int vmap, int32_t* list,

@@ -48,13 +48,18 @@ enum { V_THL = 0, V_PL, V_GL, V_THR, V_PR, V_GR, V_THP, V_GP, V_THS, V_GS, V_RHO
 // gradient has arrived, then run the cheap states back to back until the
 // chain requests its next gradient (Appendix, Alg. "bundled step as input to
 // amortized step").
+// Returns NC_ALIVE if the chain is short of tstop afterwards, plus NC_INDRAW
+// if it is also still inside its draw (synchronized runtimes).  Gradient
+// requests (the steps) are counted by the compaction.
+enum NutsChainBits { NC_ALIVE = 1, NC_INDRAW = 2 };
+
 template <int EPL>
-__device__ __forceinline__ void nuts_chain_step(const NutsK& a, int c, int lane)
+__device__ __forceinline__ int nuts_chain_step(const NutsK& a, int c, int lane)
 {
     uint32_t t = a.t[c];
     if (t >= a.tstop) {
         if (lane == 0) a.req[c] = 0;
-        return;
+        return 0;
     }
     float* Vc = a.V + (size_t)c * a.nvec * a.Dp;
     auto vec = [&](int i) { return Vc + (size_t)i * a.Dp; };
@@ -64,15 +69,23 @@ __device__ __forceinline__ void nuts_chain_step(const NutsK& a, int c, int lane)
     const bool release = a.mode != 0 && a.wctr[(a.step + 2) % 3] == 0u;
     const float he = 0.5f * a.eps;
     int req = 0;
-    unsigned long long steps = 0;
+
+    // Edge vectors (theta, p, grad U) of the side(s) in `cside` held in registers
+    // (bit 1: left edge, bit 2: right edge), so INTEGRATE need not reload what
+    // this invocation has just computed or read.
+    WaveVec<EPL> cth, cp, cg;
+    int cside = 0;
 
     // 1) the leapfrog whose gradient has arrived
     if (fl & NF_PENDING) {
         const int eth = v > 0 ? V_THR : V_THL, ep = v > 0 ? V_PR : V_PL, eg = v > 0 ? V_GR : V_GL;
         const float vhe = (float)v * he;
-        WaveVec<EPL> g, p, ph;
+        // independent loads issued together: gradient, half-step momentum, new edge position, rho_sub
+        WaveVec<EPL> g, p, ph, th, rs;
         g.load(a.Gres + (size_t)c * a.Dp, lane);
         ph.load(vec(V_PH), lane);
+        th.load(vec(eth), lane);
+        rs.load(vec(V_RHOS), lane);
 #pragma unroll
         for (int e = 0; e < EPL; ++e) p.r[e] = ph.r[e] - vhe * g.r[e];
         const float Un = a.Ures[c];
@@ -86,15 +99,11 @@ __device__ __forceinline__ void nuts_chain_step(const NutsK& a, int c, int lane)
             const float Wn = logaddexp_f(Ws, w);
             if (logf(uniform<float>(a.seed, (uint32_t)c, t, ROLE_LEAF, ((uint32_t)j << 16) | (uint32_t)nn)) <
                 w - Wn) {
-                WaveVec<EPL> th;
-                th.load(vec(eth), lane);
                 th.store(vec(V_THS), lane);
                 g.store(vec(V_GS), lane);
                 US = Un;
             }
             Ws = Wn;
-            WaveVec<EPL> rs;
-            rs.load(vec(V_RHOS), lane);
 #pragma unroll
             for (int e = 0; e < EPL; ++e) rs.r[e] += p.r[e];
             rs.store(vec(V_RHOS), lane);
@@ -119,6 +128,10 @@ __device__ __forceinline__ void nuts_chain_step(const NutsK& a, int c, int lane)
             }
             if (!(fl & NF_INVALID)) ++nn;
         }
+        cth = th;
+        cp = p;
+        cg = g;
+        cside = v > 0 ? 2 : 1;
         fl &= ~NF_PENDING;
         k = (!(fl & NF_INVALID) && nn < (1 << j)) ? NS_INTEGRATE : NS_CHECK;
     }
@@ -130,7 +143,9 @@ __device__ __forceinline__ void nuts_chain_step(const NutsK& a, int c, int lane)
             k = NS_INIT;
         }
         if (k == NS_INIT) {
-            WaveVec<EPL> p0;
+            WaveVec<EPL> p0, th, g;
+            th.load(vec(V_THP), lane);
+            g.load(vec(V_GP), lane);
 #pragma unroll
             for (int e = 0; e < EPL; ++e) {
                 const int d = e * 64 + lane;
@@ -140,13 +155,14 @@ __device__ __forceinline__ void nuts_chain_step(const NutsK& a, int c, int lane)
             p0.store(vec(V_PL), lane);
             p0.store(vec(V_PR), lane);
             p0.store(vec(V_RHO), lane);
-            WaveVec<EPL> th, g;
-            th.load(vec(V_THP), lane);
-            g.load(vec(V_GP), lane);
             th.store(vec(V_THL), lane);
             th.store(vec(V_THR), lane);
             g.store(vec(V_GL), lane);
             g.store(vec(V_GR), lane);
+            cth = th;
+            cp = p0;
+            cg = g;
+            cside = 3;
             W = 0.0f;
             j = 0;
             fl = 0;
@@ -171,9 +187,15 @@ __device__ __forceinline__ void nuts_chain_step(const NutsK& a, int c, int lane)
             const int eth = v > 0 ? V_THR : V_THL, ep = v > 0 ? V_PR : V_PL, eg = v > 0 ? V_GR : V_GL;
             const float vhe = (float)v * he, veps = (float)v * a.eps;
             WaveVec<EPL> th, p, g, ph;
-            th.load(vec(eth), lane);
-            p.load(vec(ep), lane);
-            g.load(vec(eg), lane);
+            if (cside & (v > 0 ? 2 : 1)) {
+                th = cth;
+                p = cp;
+                g = cg;
+            } else {
+                th.load(vec(eth), lane);
+                p.load(vec(ep), lane);
+                g.load(vec(eg), lane);
+            }
 #pragma unroll
             for (int e = 0; e < EPL; ++e) {
                 ph.r[e] = p.r[e] - vhe * g.r[e];
@@ -185,7 +207,6 @@ __device__ __forceinline__ void nuts_chain_step(const NutsK& a, int c, int lane)
             fl |= NF_PENDING;
             req = 1;
             --budget;
-            ++steps;
             break;
         }
         if (k == NS_CHECK) {
@@ -207,8 +228,14 @@ __device__ __forceinline__ void nuts_chain_step(const NutsK& a, int c, int lane)
 #pragma unroll
                 for (int e = 0; e < EPL; ++e) rho.r[e] += rs.r[e];
                 rho.store(vec(V_RHO), lane);
-                pl.load(vec(V_PL), lane);
-                pr.load(vec(V_PR), lane);
+                if (cside & 1)
+                    pl = cp;
+                else
+                    pl.load(vec(V_PL), lane);
+                if (cside & 2)
+                    pr = cp;
+                else
+                    pr.load(vec(V_PR), lane);
                 if (wdot(pl, rho) <= 0.0f || wdot(pr, rho) <= 0.0f) fl |= NF_STOP | NF_TURNED;
             }
             ++j;
@@ -251,12 +278,9 @@ __device__ __forceinline__ void nuts_chain_step(const NutsK& a, int c, int lane)
         a.UP[c] = UP;
         a.US[c] = US;
         a.req[c] = req;
-        if (steps) atomicAdd(&a.ctr[0], steps);
-        if (t < a.tstop) {
-            atomicAdd(&a.wctr[3 + a.step % 3], 1u);
-            if (a.mode != 0 && k != NS_WAIT) atomicAdd(&a.wctr[a.step % 3], 1u);
-        }
     }
+    if (t >= a.tstop) return 0;
+    return NC_ALIVE | ((a.mode != 0 && k != NS_WAIT) ? NC_INDRAW : 0);
 }
 
 // Chains of one job that asked for a gradient, in chain order (one block of
@@ -284,7 +308,10 @@ __device__ __forceinline__ void nuts_compact_block(const int32_t* req, int m, in
     if (vmap) {
         if (tid == 0) {
             *count = total > 0 ? m : 0;
-            if (total > 0) atomicAdd(&ctr[1], (unsigned long long)(m - total));
+            if (total > 0) {
+                atomicAdd(&ctr[0], (unsigned long long)total);
+                atomicAdd(&ctr[1], (unsigned long long)(m - total));
+            }
         }
         if (total > 0)
             for (int i = tid; i < m; i += 1024) list[i] = i;
@@ -293,7 +320,10 @@ __device__ __forceinline__ void nuts_compact_block(const int32_t* req, int m, in
     int pos = part[tid] - local;
     for (int i = b; i < e; ++i)
         if (req[i]) list[pos++] = i;
-    if (tid == 0) *count = total;
+    if (tid == 0) {
+        *count = total;
+        if (total > 0) atomicAdd(&ctr[0], (unsigned long long)total);
+    }
 }
 
 inline NutsK nuts_view(const JobDev& j, int mode, uint32_t step)
