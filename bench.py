@@ -42,18 +42,25 @@ METRIC = "draws/sec FSM vs synchronized (ESS, NUTS, 8192 chains); p50/p99 job la
 PEAK_MFMA_F32 = 157.3  # TFLOP/s, MI355X dense FP32 MFMA
 
 
+def gemm_source_digest():
+    """SHA-256 of the ellipse GEMM's device function (the text of nu_gemm_block)."""
+    src = open(os.path.join(ROOT, "paper_2503_17405_amd", "csrc", "ess_device.h")).read()
+    a = src.index("template <int RT, int CT = 2>\n__device__ __forceinline__ void nu_gemm_block(")
+    b = src.index("// ------------------------------------------------------------ ESS blocks", a)
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
 def stored_traffic():
     """HBM bytes per full-window launch of the ellipse GEMM, from the committed rocprofv3
     counter summary -- None if the kernel source changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "nu_gemm_d1024_traffic.md")
-    src = os.path.join(ROOT, "paper_2503_17405_amd", "csrc", "ess_device.h")
     try:
         txt = open(path).read()
-        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    except OSError:
+        cur = gemm_source_digest()
+    except (OSError, ValueError):
         return None
     m1 = re.search(r"traffic_bytes_per_launch: (\d+)", txt)
-    m2 = re.search(r"source_sha256 \(.*?\): ([0-9a-f]{64})", txt)
+    m2 = re.search(r"nu_gemm_block source sha256: ([0-9a-f]{64})", txt)
     if not (m1 and m2) or m2.group(1) != cur:
         return None
     return int(m1.group(1))

@@ -120,29 +120,38 @@ __global__ __launch_bounds__(256) void batch_fsm_kernel(const BJob* jobs_in, con
         if (cls <= BC_ESS16) {
             const EssK<float>& a = *(const EssK<float>*)&jobs[item.job].ess;
             uint32_t de = 0;
+            EssTally tl;
             switch (cls) {
-            case BC_ESS1: de = ess_window<float, 1>(a, item.first, lane); break;
-            case BC_ESS2: de = ess_window<float, 2>(a, item.first, lane); break;
-            case BC_ESS4: de = ess_window<float, 4>(a, item.first, lane); break;
-            case BC_ESS6: de = ess_window<float, 6>(a, item.first, lane); break;
-            case BC_ESS8: de = ess_window<float, 8>(a, item.first, lane); break;
-            case BC_ESS12: de = ess_window<float, 12>(a, item.first, lane); break;
-            default: de = ess_window<float, 16>(a, item.first, lane); break;
+            case BC_ESS1: de = ess_window<float, 1>(a, item.first, lane, tl); break;
+            case BC_ESS2: de = ess_window<float, 2>(a, item.first, lane, tl); break;
+            case BC_ESS4: de = ess_window<float, 4>(a, item.first, lane, tl); break;
+            case BC_ESS6: de = ess_window<float, 6>(a, item.first, lane, tl); break;
+            case BC_ESS8: de = ess_window<float, 8>(a, item.first, lane, tl); break;
+            case BC_ESS12: de = ess_window<float, 12>(a, item.first, lane, tl); break;
+            default: de = ess_window<float, 16>(a, item.first, lane, tl); break;
             }
+            ess_count(a, tl, lane);
             if (lane == 0) nd += de;
         } else if (cls <= BC_DR16) {
             const DrK& a = *(const DrK*)&jobs[item.job].dr;
             const int c = item.first + lane;
+            uint32_t steps = 0, live = 0;
             if (c < a.m) {
                 const uint32_t stop = a.t[c] + jobs[item.job].chunk;
                 if (cls == BC_DR4)
-                    nd += dr_run<4>(a, c, stop);
+                    nd += dr_run<4>(a, c, stop, &steps, &live);
                 else if (cls == BC_DR8)
-                    nd += dr_run<8>(a, c, stop);
+                    nd += dr_run<8>(a, c, stop, &steps, &live);
                 else if (!WIDE || cls == BC_DR12)
-                    nd += dr_run<12>(a, c, stop);
+                    nd += dr_run<12>(a, c, stop, &steps, &live);
                 else
-                    nd += dr_run<WIDE ? 16 : 12>(a, c, stop);
+                    nd += dr_run<WIDE ? 16 : 12>(a, c, stop, &steps, &live);
+            }
+            // one atomic per wave and counter
+            const unsigned long long st = wave_sum_u64(steps), lv = wave_sum_u64(live);
+            if (lane == 0) {
+                if (st) atomicAdd(&a.ctr[0], st);
+                if (lv) atomicAdd(&a.ctr[4], lv);
             }
         }
     }

@@ -20,19 +20,23 @@
 
 namespace fsmmc {
 
+// Counters are summed per wave and block: one atomic per block and counter.
 template <int NM>
 __global__ __launch_bounds__(256) void dr_fsm_kernel(DrK a)
 {
+    __shared__ unsigned long long s_sum;
     const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (c >= a.m) return;
-    (void)dr_run<NM>(a, c, a.tstop);
+    uint32_t steps = 0, live = 0;
+    if (c < a.m) (void)dr_run<NM>(a, c, a.tstop, &steps, &live);
+    const unsigned long long st = block_sum_u64(wave_sum_u64(steps), &s_sum);
+    if (threadIdx.x == 0 && st) atomicAdd(&a.ctr[0], st);
+    const unsigned long long lv = block_sum_u64(wave_sum_u64(live), &s_sum);
+    if (threadIdx.x == 0 && lv) atomicAdd(&a.ctr[4], lv);
 }
 
 template <int NM>
-__global__ __launch_bounds__(256) void dr_sync_kernel(DrK a, uint32_t draw)
+__device__ __forceinline__ int dr_sync_one(const DrK& a, int c, uint32_t draw, int* stages)
 {
-    const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (c >= a.m) return;
     DrLane<NM> L;
     dr_load<NM>(a, c, L);
     int steps = 0;
@@ -41,22 +45,34 @@ __global__ __launch_bounds__(256) void dr_sync_kernel(DrK a, uint32_t draw)
         ++steps;
         if (end) break;
     }
-    atomicMax(&a.maxN[draw], L.s);
+    *stages = L.s;
     dr_emit<NM>(a, c, L);
     dr_store<NM>(a, c, L);
-    atomicAdd(&a.ctr[0], (unsigned long long)steps);
+    return steps;
+}
+
+template <int NM>
+__global__ __launch_bounds__(256) void dr_sync_kernel(DrK a, uint32_t draw)
+{
+    __shared__ unsigned long long s_sum;
+    __shared__ int s_max;
+    const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    int steps = 0, stages = 0;
+    if (c < a.m) steps = dr_sync_one<NM>(a, c, draw, &stages);
+    const int mx = block_max_i32(wave_max_i32(stages), &s_max);
+    if (threadIdx.x == 0) atomicMax(&a.maxN[draw], mx);
+    const unsigned long long st = block_sum_u64(wave_sum_u64((unsigned long long)steps), &s_sum);
+    if (threadIdx.x == 0 && st) atomicAdd(&a.ctr[0], st);
 }
 
 // The stage bodies a batched while loop runs after chain c has finished
 // draw `draw`: proposal, density and acceptance, discarded.
 template <int NM>
-__global__ __launch_bounds__(256) void dr_pad_kernel(DrK a, uint32_t draw)
+__device__ __forceinline__ int dr_pad_one(const DrK& a, int c, uint32_t draw)
 {
-    const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (c >= a.m) return;
     const int done = a.counts[(size_t)c * a.n + draw];
     const int extra = a.maxN[draw] - done;
-    if (extra <= 0) return;
+    if (extra <= 0) return 0;
     DrLane<NM> L;
     dr_load<NM>(a, c, L);
     L.t = draw;
@@ -68,7 +84,18 @@ __global__ __launch_bounds__(256) void dr_pad_kernel(DrK a, uint32_t draw)
         acc += dr_logpdf<NM>(a, y) + logf(uniform<float>(a.seed, (uint32_t)c, draw, ROLE_ACC, (uint32_t)L.s));
     }
     a.sink[c] = acc;
-    atomicAdd(&a.ctr[1], (unsigned long long)extra);
+    return extra;
+}
+
+template <int NM>
+__global__ __launch_bounds__(256) void dr_pad_kernel(DrK a, uint32_t draw)
+{
+    __shared__ unsigned long long s_sum;
+    const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    int extra = 0;
+    if (c < a.m) extra = dr_pad_one<NM>(a, c, draw);
+    const unsigned long long tot = block_sum_u64(wave_sum_u64((unsigned long long)extra), &s_sum);
+    if (threadIdx.x == 0 && tot) atomicAdd(&a.ctr[1], tot);
 }
 
 // Default starts: an exact funnel draw (v = 3 z0, x_i = e^{v/2} z_i) or N(0, I).

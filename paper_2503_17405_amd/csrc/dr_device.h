@@ -210,17 +210,18 @@ __device__ __forceinline__ void dr_emit(const DrK& a, int c, DrLane<NM>& L)
 }
 
 // One lane runs chain c through PROPOSE steps until it reaches draw `stop`
-// (or n) or spends its budget.  Returns the draws it emitted.  Counters:
-// [0] steps, [4] chains still short of n.
+// (or n) or spends its budget.  Returns the draws it emitted; *steps gets the
+// steps taken and *live whether the chain is still short of n (the caller
+// adds them to the job counters [0] and [4]).
 template <int NM>
-__device__ __forceinline__ uint32_t dr_run(const DrK& a, int c, uint32_t stop)
+__device__ __forceinline__ uint32_t dr_run(const DrK& a, int c, uint32_t stop, uint32_t* steps_out, uint32_t* live)
 {
     DrLane<NM> L;
     dr_load<NM>(a, c, L);
     const uint32_t t0 = L.t;
     stop = min(stop, (uint32_t)a.n);
     int64_t budget = a.budget[c];
-    unsigned long long steps = 0;
+    uint32_t steps = 0;
     while (L.t < stop && budget > 0) {
         const int end = dr_stage<NM>(a, c, L);
         ++steps;
@@ -229,8 +230,8 @@ __device__ __forceinline__ uint32_t dr_run(const DrK& a, int c, uint32_t stop)
     }
     dr_store<NM>(a, c, L);
     a.budget[c] = budget;
-    atomicAdd(&a.ctr[0], steps);
-    if (L.t < (uint32_t)a.n) atomicAdd(&a.ctr[4], 1ull);
+    *steps_out = steps;
+    *live = L.t < (uint32_t)a.n ? 1u : 0u;
     return L.t - t0;
 }
 

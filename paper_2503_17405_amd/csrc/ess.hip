@@ -62,20 +62,29 @@ __global__ __launch_bounds__(256) void nu_gemm_simple_kernel(NuK<T> a)
 template <typename T, int EPL>
 __global__ __launch_bounds__(256) void ess_fsm_kernel(EssK<T> a)
 {
+    __shared__ unsigned long long s_sum;
     const int lane = threadIdx.x & 63;
     const int j = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
-    if (j >= a.m) return;
-    (void)ess_window<T, EPL>(a, j, lane);
+    EssTally tl;
+    if (j < a.m) (void)ess_window<T, EPL>(a, j, lane, tl);
+    // one atomic per block and counter
+    const unsigned long long steps = block_sum_u64(tl.steps, &s_sum);
+    if (threadIdx.x == 0 && steps) atomicAdd(&a.ctr[0], steps);
+    const unsigned long long guards = block_sum_u64(tl.guards, &s_sum);
+    if (threadIdx.x == 0 && guards) atomicAdd(&a.ctr[2], guards);
+    const unsigned long long live = block_sum_u64(tl.live, &s_sum);
+    if (threadIdx.x == 0 && live) atomicAdd(&a.ctr[4], live);
+    const unsigned long long left = block_sum_u64(tl.budget_left, &s_sum);
+    if (threadIdx.x == 0 && left) atomicAdd(&a.ctr[3], left);
 }
 
 // ------------------------------------------------------------ synchronized
 // One draw of every chain (all chains at `draw`, at a draw boundary).
+// Chain j's draw `draw` (one wave); returns its evaluations, sets *rejected.
 template <typename T, int EPL>
-__global__ __launch_bounds__(256) void ess_sync_kernel(EssK<T> a, uint32_t draw, uint32_t slot)
+__device__ __forceinline__ int ess_sync_one(const EssK<T>& a, int j, int lane, uint32_t draw, uint32_t slot,
+                                            bool* rejected)
 {
-    const int lane = threadIdx.x & 63;
-    const int j = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
-    if (j >= a.m) return;
     T x[EPL], nu[EPL], xp[EPL], yv[EPL];
     const T* xj = a.x + (size_t)j * a.Dp;
     const T* nj = a.nu + ((size_t)j * a.W + slot) * a.Dp;
@@ -108,23 +117,38 @@ __global__ __launch_bounds__(256) void ess_sync_kernel(EssK<T> a, uint32_t draw,
     if (lane == 0) {
         a.lx[j] = lx;
         a.t[j] = draw + 1;
-        atomicAdd(&a.ctr[0], (unsigned long long)evals);
-        if (!accept) atomicAdd(&a.ctr[2], 1ull);
-        atomicMax(&a.maxN[draw], evals);
     }
+    *rejected = !accept;
+    return evals;
+}
+
+template <typename T, int EPL>
+__global__ __launch_bounds__(256) void ess_sync_kernel(EssK<T> a, uint32_t draw, uint32_t slot)
+{
+    __shared__ unsigned long long s_sum;
+    __shared__ int s_max;
+    const int lane = threadIdx.x & 63;
+    const int j = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+    int evals = 0;
+    bool rejected = false;
+    if (j < a.m) evals = ess_sync_one<T, EPL>(a, j, lane, draw, slot, &rejected);
+    // one atomic per block and counter
+    const unsigned long long steps = block_sum_u64((unsigned long long)evals, &s_sum);
+    if (threadIdx.x == 0 && steps) atomicAdd(&a.ctr[0], steps);
+    const unsigned long long rej = block_sum_u64(rejected ? 1ull : 0ull, &s_sum);
+    if (threadIdx.x == 0 && rej) atomicAdd(&a.ctr[2], rej);
+    const int mx = block_max_i32(evals, &s_max);
+    if (threadIdx.x == 0) atomicMax(&a.maxN[draw], mx);
 }
 
 // The loop bodies a batched while loop runs for chain j after its own exit:
 // max_j N_j - N_j more proposals and log-likelihood evaluations, discarded.
 template <typename T, int EPL>
-__global__ __launch_bounds__(256) void ess_pad_kernel(EssK<T> a, uint32_t draw, uint32_t slot)
+__device__ __forceinline__ int ess_pad_one(const EssK<T>& a, int j, int lane, uint32_t draw, uint32_t slot)
 {
-    const int lane = threadIdx.x & 63;
-    const int j = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
-    if (j >= a.m) return;
     const int nj_evals = a.counts[(size_t)j * a.n + draw];
     const int extra = a.maxN[draw] - nj_evals;
-    if (extra <= 0) return;
+    if (extra <= 0) return 0;
     T x[EPL], nu[EPL], xp[EPL], yv[EPL];
     const T* xj = a.x + (size_t)j * a.Dp;
     const T* nj = a.nu + ((size_t)j * a.W + slot) * a.Dp;
@@ -140,10 +164,20 @@ __global__ __launch_bounds__(256) void ess_pad_kernel(EssK<T> a, uint32_t draw, 
                                                     (uint32_t)(nj_evals + i));
         sum += ess_propose_eval<T, EPL>(x, nu, xp, yv, theta, lane, a.D, a.target, a.inv2v);
     }
-    if (lane == 0) {
-        a.sink[j] = sum;
-        atomicAdd(&a.ctr[1], (unsigned long long)extra);
-    }
+    if (lane == 0) a.sink[j] = sum;
+    return extra;
+}
+
+template <typename T, int EPL>
+__global__ __launch_bounds__(256) void ess_pad_kernel(EssK<T> a, uint32_t draw, uint32_t slot)
+{
+    __shared__ unsigned long long s_sum;
+    const int lane = threadIdx.x & 63;
+    const int j = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+    int extra = 0;
+    if (j < a.m) extra = ess_pad_one<T, EPL>(a, j, lane, draw, slot);
+    const unsigned long long tot = block_sum_u64((unsigned long long)extra, &s_sum);
+    if (threadIdx.x == 0 && tot) atomicAdd(&a.ctr[1], tot);
 }
 
 // ------------------------------------------------------------ host side

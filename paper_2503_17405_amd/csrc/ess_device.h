@@ -276,12 +276,18 @@ __device__ __forceinline__ void ess_emit(const EssK<T>& a, int j, uint32_t t, co
     if (lane == 0) a.counts[(size_t)j * a.n + t] = evals;
 }
 
+// What one chain's window adds to the job counters: [0] steps, [2] guard
+// trips, [4] chains still short of n, [3] of those, chains with budget left.
+struct EssTally {
+    uint32_t steps = 0, guards = 0, live = 0, budget_left = 0;
+};
+
 // One wave runs chain j through FSM steps until it has used the ellipse
 // window [t0, t0 + W), reached n draws, or spent its step budget.  Returns
-// the number of draws it emitted.  Counters: [0] steps, [2] guard trips,
-// [4] chains still short of n, [3] of those, chains with budget left.
+// the number of draws it emitted; the counter contributions go to tl (the
+// caller adds them to the job's counters).
 template <typename T, int EPL>
-__device__ __forceinline__ uint32_t ess_window(const EssK<T>& a, int j, int lane)
+__device__ __forceinline__ uint32_t ess_window(const EssK<T>& a, int j, int lane, EssTally& tl)
 {
     uint32_t t = a.t[j];
     if (t >= (uint32_t)a.n) return 0;
@@ -348,14 +354,23 @@ __device__ __forceinline__ uint32_t ess_window(const EssK<T>& a, int j, int lane
         a.logy[j] = logy;
         a.lx[j] = lx;
         a.budget[j] = budget;
-        atomicAdd(&a.ctr[0], steps);
-        if (guards) atomicAdd(&a.ctr[2], (unsigned long long)guards);
-        if (t < (uint32_t)a.n) {
-            atomicAdd(&a.ctr[4], 1ull);
-            if (budget > 0) atomicAdd(&a.ctr[3], 1ull);
-        }
     }
+    tl.steps = (uint32_t)steps;
+    tl.guards = (uint32_t)guards;
+    tl.live = t < (uint32_t)a.n ? 1u : 0u;
+    tl.budget_left = (tl.live && budget > 0) ? 1u : 0u;
     return t - t0;
+}
+
+// Add one chain's tally to the job counters (lane 0 of its wave).
+template <typename T>
+__device__ __forceinline__ void ess_count(const EssK<T>& a, const EssTally& tl, int lane)
+{
+    if (lane != 0) return;
+    if (tl.steps) atomicAdd(&a.ctr[0], (unsigned long long)tl.steps);
+    if (tl.guards) atomicAdd(&a.ctr[2], (unsigned long long)tl.guards);
+    if (tl.live) atomicAdd(&a.ctr[4], 1ull);
+    if (tl.budget_left) atomicAdd(&a.ctr[3], 1ull);
 }
 
 // ------------------------------------------------------------ host views

@@ -141,6 +141,42 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Wave-wide sums for counters (every lane gets the total).
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i32(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Block-wide sum of per-wave counters: every thread of the block must call it
+// (lane 0 of each wave contributes v); thread 0 gets the total.  Replaces one
+// same-address atomic per wave by one per block.
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v, unsigned long long* s_slot)
+{
+    if (threadIdx.x == 0) *s_slot = 0;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(s_slot, v);
+    __syncthreads();
+    return *s_slot;
+}
+
+__device__ __forceinline__ int block_max_i32(int v, int* s_slot)
+{
+    if (threadIdx.x == 0) *s_slot = 0;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) atomicMax(s_slot, v);
+    __syncthreads();
+    return *s_slot;
+}
+
 // A D-vector held by one wave: element d = e * 64 + lane.
 template <int EPL>
 struct WaveVec {
