@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void ess_fsm_kernel(EssK<T> a)
 {
     __shared__ unsigned long long s_sum;
     const int lane = threadIdx.x & 63;
-    const int j = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const int j = uni((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
     EssTally tl;
     if (j < a.m) (void)ess_window<T, EPL>(a, j, lane, tl);
     // one atomic per block and counter
@@ -94,12 +94,12 @@ __device__ __forceinline__ int ess_sync_one(const EssK<T>& a, int j, int lane, u
         yv[e] = a.y[e * 64 + lane];
         nu[e] = nj[e * 64 + lane];
     }
-    T lx = a.lx[j], logy, theta, tmin, tmax;
+    T lx = uni(a.lx[j]), logy, theta, tmin, tmax;
     ess_begin<T>(a.seed, (uint32_t)j, draw, lx, logy, theta, tmin, tmax);
     int evals = 0;
     T lp;
     for (;;) {
-        lp = ess_propose_eval<T, EPL>(x, nu, xp, yv, theta, lane, a.D, a.target, a.inv2v);
+        lp = uni(ess_propose_eval<T, EPL>(x, nu, xp, yv, theta, lane, a.D, a.target, a.inv2v));
         ++evals;
         if (lp > logy || evals >= kEssMaxEvals) break;
         ess_shrink<T>(a.seed, (uint32_t)j, draw, evals, theta, tmin, tmax);
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void ess_sync_kernel(EssK<T> a, uint32_t draw,
     __shared__ unsigned long long s_sum;
     __shared__ int s_max;
     const int lane = threadIdx.x & 63;
-    const int j = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const int j = uni((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
     int evals = 0;
     bool rejected = false;
     if (j < a.m) evals = ess_sync_one<T, EPL>(a, j, lane, draw, slot, &rejected);
@@ -146,8 +146,8 @@ __global__ __launch_bounds__(256) void ess_sync_kernel(EssK<T> a, uint32_t draw,
 template <typename T, int EPL>
 __device__ __forceinline__ int ess_pad_one(const EssK<T>& a, int j, int lane, uint32_t draw, uint32_t slot)
 {
-    const int nj_evals = a.counts[(size_t)j * a.n + draw];
-    const int extra = a.maxN[draw] - nj_evals;
+    const int nj_evals = uni(a.counts[(size_t)j * a.n + draw]);
+    const int extra = uni(a.maxN[draw]) - nj_evals;
     if (extra <= 0) return 0;
     T x[EPL], nu[EPL], xp[EPL], yv[EPL];
     const T* xj = a.x + (size_t)j * a.Dp;
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void ess_pad_kernel(EssK<T> a, uint32_t draw, 
 {
     __shared__ unsigned long long s_sum;
     const int lane = threadIdx.x & 63;
-    const int j = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const int j = uni((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
     int extra = 0;
     if (j < a.m) extra = ess_pad_one<T, EPL>(a, j, lane, draw, slot);
     const unsigned long long tot = block_sum_u64((unsigned long long)extra, &s_sum);

@@ -164,22 +164,17 @@ __device__ __forceinline__ void nu_gemm_block(const NuK<float>& a, int col0)
         __syncthreads();
         buf ^= 1;
     }
+    // column g = chain * W + w is stored at out[g * Dp + row]
 #pragma unroll
-    for (int r = 0; r < RT; ++r) {
-        const int ti = tiles[r];
-        if (ti < 0) continue;
-        const int row = 32 * ti + l32;
+    for (int c = 0; c < CT; ++c) {
 #pragma unroll
-        for (int c = 0; c < CT; ++c) {
+        for (int q = 0; q < 16; ++q) {
+            const int g = col0 + c * 32 + 8 * (q >> 2) + 4 * h + (q & 3);
+            if (g >= ncols) continue;
+            float* o = a.out + (size_t)g * a.Dp + l32;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int col = c * 32 + 8 * (q >> 2) + 4 * h + (q & 3);
-                const int g = col0 + col;
-                if (g < ncols) {
-                    const int ch = g / a.W, w = g - ch * a.W;
-                    a.out[((size_t)ch * a.W + w) * a.Dp + row] = acc[r][c][q];
-                }
-            }
+            for (int r = 0; r < RT; ++r)
+                if (tiles[r] >= 0) o[32 * tiles[r]] = acc[r][c][q];
         }
     }
 }
@@ -289,13 +284,15 @@ struct EssTally {
 template <typename T, int EPL>
 __device__ __forceinline__ uint32_t ess_window(const EssK<T>& a, int j, int lane, EssTally& tl)
 {
-    uint32_t t = a.t[j];
+    j = uni(j);
+    uint32_t t = uni(a.t[j]);
     if (t >= (uint32_t)a.n) return 0;
     const uint32_t t0 = t;
     const uint32_t wend = min(t0 + (uint32_t)a.W, (uint32_t)a.n);
-    int k = a.k[j], evals = a.evals[j];
-    T theta = a.theta[j], tmin = a.tmin[j], tmax = a.tmax[j], logy = a.logy[j], lx = a.lx[j];
-    int64_t budget = a.budget[j];
+    int k = uni(a.k[j]), evals = uni(a.evals[j]);
+    T theta = uni(a.theta[j]), tmin = uni(a.tmin[j]), tmax = uni(a.tmax[j]), logy = uni(a.logy[j]),
+      lx = uni(a.lx[j]);
+    int64_t budget = uni((int64_t)a.budget[j]);
 
     T x[EPL], nu[EPL], xp[EPL], yv[EPL];
     const T* xj = a.x + (size_t)j * a.Dp;
@@ -320,7 +317,7 @@ __device__ __forceinline__ uint32_t ess_window(const EssK<T>& a, int j, int lane
         } else {
             ess_shrink<T>(a.seed, (uint32_t)j, t, evals, theta, tmin, tmax);
         }
-        const T lp = ess_propose_eval<T, EPL>(x, nu, xp, yv, theta, lane, a.D, a.target, a.inv2v);
+        const T lp = uni(ess_propose_eval<T, EPL>(x, nu, xp, yv, theta, lane, a.D, a.target, a.inv2v));
         ++evals;
         ++steps;
         --budget;

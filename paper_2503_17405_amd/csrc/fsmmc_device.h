@@ -141,6 +141,26 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Lane 0's copy of a value every active lane already holds (a chain's
+// scalar state when one wave runs one chain).  The value is unchanged; the
+// compiler may then keep it in scalar registers and run integer work on it
+// (the Philox rounds of a chain's angle draws) on the scalar unit instead of
+// the vector ALU.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ int64_t uni(int64_t v)
+{
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ __forceinline__ double uni(double v)
+{
+    return __longlong_as_double((long long)uni((int64_t)__double_as_longlong(v)));
+}
+
 // Wave-wide sums for counters (every lane gets the total).
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 {
@@ -193,14 +213,15 @@ struct WaveVec {
     }
 };
 
-// Dot product of two wave vectors (lane-local sum over e, then the butterfly).
+// Dot product of two wave vectors (lane-local sum over e, then the butterfly);
+// wave-uniform (called by whole waves only).
 template <int EPL>
 __device__ __forceinline__ float wdot(const WaveVec<EPL>& a, const WaveVec<EPL>& b)
 {
     float s = 0.0f;
 #pragma unroll
     for (int e = 0; e < EPL; ++e) s += a.r[e] * b.r[e];
-    return wave_sum(s);
+    return uni(wave_sum(s));
 }
 
 // ---------------------------------------------------------------- math

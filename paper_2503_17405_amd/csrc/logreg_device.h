@@ -116,7 +116,7 @@ __device__ __forceinline__ void logreg_grad_tile(const GradK& a, int ct, int sl)
                 const float v = e[i];
                 const float yv = a.y[row];
                 const float ex = __expf(-fabsf(v));
-                const float inv = __frcp_rn(1.0f + ex);
+                const float inv = __builtin_amdgcn_rcpf(1.0f + ex);  // hardware reciprocal, 1 ulp
                 const float sig = v >= 0.0f ? inv : ex * inv;
                 lin += ok ? (yv * v - fmaxf(v, 0.0f)) : 0.0f;
                 prod *= ok ? 1.0f + ex : 1.0f;

@@ -56,17 +56,19 @@ enum NutsChainBits { NC_ALIVE = 1, NC_INDRAW = 2 };
 template <int EPL>
 __device__ __forceinline__ int nuts_chain_step(const NutsK& a, int c, int lane)
 {
-    uint32_t t = a.t[c];
+    c = uni(c);
+    uint32_t t = uni(a.t[c]);
     if (t >= a.tstop) {
         if (lane == 0) a.req[c] = 0;
         return 0;
     }
     float* Vc = a.V + (size_t)c * a.nvec * a.Dp;
     auto vec = [&](int i) { return Vc + (size_t)i * a.Dp; };
-    int k = a.k[c], j = a.jd[c], v = a.v[c], nn = a.nn[c], fl = a.flags[c], nleap = a.nleap[c];
-    int64_t budget = a.budget[c];
-    float H0 = a.H0[c], W = a.W[c], Ws = a.Ws[c], UP = a.UP[c], US = a.US[c];
-    const bool release = a.mode != 0 && a.wctr[(a.step + 2) % 3] == 0u;
+    int k = uni(a.k[c]), j = uni(a.jd[c]), v = uni(a.v[c]), nn = uni(a.nn[c]), fl = uni(a.flags[c]),
+        nleap = uni(a.nleap[c]);
+    int64_t budget = uni((int64_t)a.budget[c]);
+    float H0 = uni(a.H0[c]), W = uni(a.W[c]), Ws = uni(a.Ws[c]), UP = uni(a.UP[c]), US = uni(a.US[c]);
+    const bool release = a.mode != 0 && uni(a.wctr[(a.step + 2) % 3]) == 0u;
     const float he = 0.5f * a.eps;
     int req = 0;
 
@@ -88,7 +90,7 @@ __device__ __forceinline__ int nuts_chain_step(const NutsK& a, int c, int lane)
         rs.load(vec(V_RHOS), lane);
 #pragma unroll
         for (int e = 0; e < EPL; ++e) p.r[e] = ph.r[e] - vhe * g.r[e];
-        const float Un = a.Ures[c];
+        const float Un = uni(a.Ures[c]);
         ++nleap;
         const float w = H0 - (Un + 0.5f * wdot(p, p));
         p.store(vec(ep), lane);
