@@ -43,9 +43,9 @@ PEAK_MFMA_F32 = 157.3  # TFLOP/s, MI355X dense FP32 MFMA
 
 
 def gemm_source_digest():
-    """SHA-256 of the ellipse GEMM's device function (the text of nu_gemm_block)."""
+    """SHA-256 of the ellipse GEMM's device code (the "ellipse GEMM" section of ess_device.h)."""
     src = open(os.path.join(ROOT, "paper_2503_17405_amd", "csrc", "ess_device.h")).read()
-    a = src.index("template <int RT, int CT = 2>\n__device__ __forceinline__ void nu_gemm_block(")
+    a = src.index("// ------------------------------------------------------------ ellipse GEMM")
     b = src.index("// ------------------------------------------------------------ ESS blocks", a)
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
@@ -60,7 +60,7 @@ def stored_traffic():
     except (OSError, ValueError):
         return None
     m1 = re.search(r"traffic_bytes_per_launch: (\d+)", txt)
-    m2 = re.search(r"nu_gemm_block source sha256: ([0-9a-f]{64})", txt)
+    m2 = re.search(r"ellipse GEMM source sha256: ([0-9a-f]{64})", txt)
     if not (m1 and m2) or m2.group(1) != cur:
         return None
     return int(m1.group(1))

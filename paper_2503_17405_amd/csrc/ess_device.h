@@ -45,7 +45,8 @@ struct EssK {
 };
 
 // ------------------------------------------------------------ ellipse GEMM
-// One block of 8 waves computes NC = 32 CT columns (col0 ..) over all Dp rows.
+// Up to 3 row tiles per wave (Dp <= 768): one block of 8 waves computes NC = 32 CT
+// columns (col0 ..) over all Dp rows.
 // Wave w owns RT row tiles of 32 rows in "snake" order (w, 15-w, 16+w, 31-w,
 // ...) so the triangular work is balanced across waves.  The K dimension is
 // walked in chunks of 32, software-pipelined: while the MFMAs of chunk k run
@@ -58,7 +59,7 @@ struct EssK {
 // order per output element do not depend on the pipelining.  A block whose
 // columns are all past their chain's last draw exits at once.
 template <int RT, int CT = 2>
-__device__ __forceinline__ void nu_gemm_block(const NuK<float>& a, int col0)
+__device__ __forceinline__ void nu_gemm_block_flat(const NuK<float>& a, int col0)
 {
     static_assert(CT == 2 || CT == 4, "64 or 128 columns per block");
     constexpr int NC = 32 * CT, ZC = CT / 2;
@@ -177,6 +178,196 @@ __device__ __forceinline__ void nu_gemm_block(const NuK<float>& a, int col0)
                 if (tiles[r] >= 0) o[32 * tiles[r]] = acc[r][c][q];
         }
     }
+}
+
+// 4 row tiles per wave (Dp <= 1024), the same products in the same order as
+// nu_gemm_block_flat with more registers: one block of 8 waves computes NC = 32 CT
+// columns (col0 ..) over all Dp rows.
+// Wave w owns RT row tiles of 32 rows in "snake" order (w, 15-w, 16+w, 31-w,
+// ...) so the triangular work is balanced across waves; it visits them from
+// the last row tile down, so the tiles that reach K chunk k are a prefix.
+// The K dimension is walked in chunks of 32 with one barrier per chunk.  Per
+// chunk a wave reads its Z operands from LDS once (shared by its row tiles),
+// loads the L rows of its next tile (float4 along k) while the MFMAs of the
+// current one run (v_mfma_f32_32x32x2f32, FP32 accumulation), and draws its
+// normals of chunk k+1 (one Philox block per thread and 64 columns) in
+// between the MFMAs of its first tile; they go to the other LDS buffer after
+// the chunk.  The MFMA computes nu^T = z^T L^T so each output register row is
+// 32 consecutive nu entries of one column (128-byte coalesced stores).  The
+// products and their order per output element do not depend on any of this
+// scheduling.  A block whose columns are all past their chain's last draw
+// exits at once.
+template <int RT, int CT = 2>
+__device__ __forceinline__ void nu_gemm_block_deep(const NuK<float>& a, int col0)
+{
+    static_assert(CT == 2 || CT == 4, "64 or 128 columns per block");
+    constexpr int NC = 32 * CT, ZC = CT / 2;
+    __shared__ float Zs[2][32][NC];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, l32 = lane & 31;
+    const int ncols = a.m * a.W;
+
+    const int zc = tid & 63, zb = tid >> 6;
+    bool zvalid[ZC];
+    int zchain[ZC];
+    uint32_t zdraw[ZC];
+    int any = 0;
+#pragma unroll
+    for (int cc = 0; cc < ZC; ++cc) {
+        const int gcol = col0 + zc + 64 * cc;
+        zvalid[cc] = gcol < ncols;
+        zchain[cc] = 0;
+        zdraw[cc] = 0;
+        if (zvalid[cc]) {
+            zchain[cc] = gcol / a.W;
+            const int zw = gcol - zchain[cc] * a.W;
+            zdraw[cc] = a.draw_fixed >= 0 ? (uint32_t)a.draw_fixed : a.t[zchain[cc]] + a.tadd + (uint32_t)zw;
+            zvalid[cc] = a.draw_fixed >= 0 || zdraw[cc] < (uint32_t)a.n;
+        }
+        any |= zvalid[cc] ? 1 : 0;
+    }
+    if (!__syncthreads_or(any)) return;
+
+    // this thread's 4 normals (rows kc + 4 zb .. + 3) per column group; +0 where
+    // the row or the column does not exist.  No branches (the mask is applied
+    // with an opaque AND), so the compiler can place them between MFMAs.
+    auto draw = [&](int kc, float (&z)[ZC][4]) {
+        const int kb = kc + 4 * zb;
+#pragma unroll
+        for (int cc = 0; cc < ZC; ++cc) {
+            normals4<float>(a.seed, (uint32_t)zchain[cc], zdraw[cc], a.role, 0, (uint32_t)(kb >> 2), z[cc]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t keep = (zvalid[cc] && kb + i < a.D) ? 0xFFFFFFFFu : 0u;
+                uint32_t bits;
+                asm("v_and_b32 %0, %1, %2" : "=v"(bits) : "v"(__float_as_uint(z[cc][i])), "v"(keep));
+                z[cc][i] = __uint_as_float(bits);
+            }
+        }
+    };
+    auto put = [&](int buf, const float (&z)[ZC][4]) {
+#pragma unroll
+        for (int cc = 0; cc < ZC; ++cc)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Zs[buf][4 * zb + i][zc + 64 * cc] = z[cc][i];
+    };
+
+    // the wave's row tiles, last first; missing ones (-1) at the end
+    const int ntiles = a.Dp >> 5;
+    int tiles[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) tiles[r] = -1;
+    int nt = 0;
+#pragma unroll
+    for (int rr = RT - 1; rr >= 0; --rr) {
+        const int idx = (rr & 1) ? rr * 8 + 7 - wave : rr * 8 + wave;
+        if (idx < ntiles) {
+#pragma unroll
+            for (int p = 0; p < RT; ++p)
+                if (p == nt) tiles[p] = idx;
+            ++nt;
+        }
+    }
+    floatx16 acc[RT][CT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[r][c][q] = 0.0f;
+    // L[32 ti + l32][kc + 16 h .. + 15]
+    auto load_l = [&](float (&lr)[16], int ti, int kc) {
+        const float4* Lr = reinterpret_cast<const float4*>(a.L + (size_t)(32 * ti + l32) * a.Dp + kc + 16 * h);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float4 q4 = Lr[v];
+            lr[4 * v + 0] = q4.x;
+            lr[4 * v + 1] = q4.y;
+            lr[4 * v + 2] = q4.z;
+            lr[4 * v + 3] = q4.w;
+        }
+    };
+
+    {
+        float z0[ZC][4];
+        draw(0, z0);
+        put(0, z0);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int kc = 0; kc < a.Dp; kc += 32) {
+        const bool more = kc + 32 < a.Dp;
+        int na = 0;  // tiles that reach this chunk: tiles[0 .. na-1]
+#pragma unroll
+        for (int r = 0; r < RT; ++r) na += (tiles[r] >= 0 && 32 * tiles[r] + 31 >= kc) ? 1 : 0;
+        na = uni(na);
+        float av[16][CT];
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) av[kk][c] = Zs[buf][16 * h + kk][c * 32 + l32];
+        float zn[ZC][4];
+        float lrA[16], lrB[16];
+        if (na > 0) {
+            load_l(lrA, tiles[0], kc);
+            load_l(lrB, 1 < na ? tiles[1] : tiles[0], kc);  // tiles[0] exists: no branch
+            draw(kc + 32, zn);
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+                for (int c = 0; c < CT; ++c)
+                    acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk][c], lrA[kk], acc[0][c], 0, 0, 0);
+            // interleave: one MFMA, then up to 6 VALU instructions (the normals)
+#pragma unroll
+            for (int i = 0; i < 16 * CT; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
+            }
+        } else {
+            draw(kc + 32, zn);
+        }
+#pragma unroll
+        for (int r = 1; r < RT; ++r) {
+            if (r >= na) break;
+            float(&cur)[16] = (r & 1) ? lrB : lrA;
+            float(&nxt)[16] = (r & 1) ? lrA : lrB;
+            if (r + 1 < na) load_l(nxt, tiles[r + 1], kc);
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+                for (int c = 0; c < CT; ++c)
+                    acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk][c], cur[kk], acc[r][c], 0, 0, 0);
+        }
+        if (more) put(buf ^ 1, zn);
+        __syncthreads();
+        buf ^= 1;
+    }
+    // column g = chain * W + w is stored at out[g * Dp + row]
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int g = col0 + c * 32 + 8 * (q >> 2) + 4 * h + (q & 3);
+            if (g >= ncols) continue;
+            float* o = a.out + (size_t)g * a.Dp + l32;
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+                if (tiles[r] >= 0) o[32 * tiles[r]] = acc[r][c][q];
+        }
+    }
+}
+
+// Ellipse-direction product for the columns col0 .. col0 + 32 CT - 1 of a window.
+// Both variants give the same bits; the deep one hides the normals and the L
+// loads behind the MFMAs and pays for it in registers, which only the 4-tile
+// shape can spare without losing waves.
+template <int RT, int CT = 2>
+__device__ __forceinline__ void nu_gemm_block(const NuK<float>& a, int col0)
+{
+    if constexpr (RT >= 4)
+        nu_gemm_block_deep<RT, CT>(a, col0);
+    else
+        nu_gemm_block_flat<RT, CT>(a, col0);
 }
 
 // ------------------------------------------------------------ ESS blocks
