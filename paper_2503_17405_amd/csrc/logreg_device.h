@@ -91,14 +91,21 @@ __device__ __forceinline__ void logreg_grad_tile(const GradK& a, int ct, int sl)
         const float* X = Xs[buf];
         // 1. eta tiles (16 rows x 16 chains), K = D rounded up to 4
         floatx4 e0 = {0.0f, 0.0f, 0.0f, 0.0f}, e1 = {0.0f, 0.0f, 0.0f, 0.0f};
+        // operands of step kk + 1 are read from LDS while the MFMAs of step kk run
+        // (the read after the last step stays inside the row: k <= DP + 3 < TP)
+        const float* xrow = X + (16 * rt + l16) * TP + q4;
+        const float* b0row = Ths + (16 * et0 + l16) * TP + q4;
+        const float* b1row = Ths + (16 * (et0 + 1) + l16) * TP + q4;
+        float xa = xrow[0], b0 = b0row[0], b1 = b1row[0];
 #pragma unroll 8
         for (int kk = 0; kk < nk4; ++kk) {
-            const int k = 4 * kk + q4;
-            const float xa = X[(16 * rt + l16) * TP + k];
-            const float b0 = Ths[(16 * et0 + l16) * TP + k];
-            const float b1 = Ths[(16 * (et0 + 1) + l16) * TP + k];
+            const float xn = xrow[4 * kk + 4], b0n = b0row[4 * kk + 4], b1n = b1row[4 * kk + 4];
+            __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the MFMAs
             e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa, b0, e0, 0, 0, 0);
             e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa, b1, e1, 0, 0, 0);
+            xa = xn;
+            b0 = b0n;
+            b1 = b1n;
         }
         // 2. r = y - sigmoid(eta) into LDS, and the log-likelihood: sum [y eta - max(eta, 0)]
         //    minus one log of the product of the four factors 1 + e^-|eta| (each in (1, 2])
