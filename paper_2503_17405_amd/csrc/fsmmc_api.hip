@@ -350,7 +350,16 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
         d.Dp = 64 * d.EPL;
         const size_t Dp = (size_t)d.Dp;
         d.N = target->n_data;
-        d.slice_rows = 512;
+        // Row slices of the gradient: about 1024 (chain tile, slice) blocks at full
+        // load -- two rounds of the blocks the chip holds at once -- with slices of
+        // 256 .. 1280 rows, a multiple of the 32-row chunk (measured at N = 10^4,
+        // m = 8192: 8 slices of 1280 rows beat 20 of 512 by 5%, 5 of 2048 lose 9%)
+        {
+            const int tiles = (m + 63) / 64;
+            const int want = std::max(1, (1024 + tiles - 1) / tiles);
+            const int rows = ((d.N + want - 1) / want + 31) / 32 * 32;
+            d.slice_rows = std::min(1280, std::max(256, rows));
+        }
         d.nslices = (d.N + d.slice_rows - 1) / d.slice_rows;
         d.Np = d.nslices * d.slice_rows;
         d.nvec = nuts_nvec(d.max_depth);

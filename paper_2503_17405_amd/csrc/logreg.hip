@@ -4,7 +4,7 @@
 //   grad U = Theta - X^T r,  U = |Theta|^2 / 2 - sum_i [y_i eta_i - softplus(eta_i)].
 // This is the amortized g of the NUTS FSM (one evaluation per step per chain).
 //
-// logreg_grad_kernel: block = 4 waves, 64 listed chains x one slice of 512 rows.
+// logreg_grad_kernel: block = 4 waves, 64 listed chains x one row slice of the job.
 // Theta (64 x Dp) is staged in LDS once.  The slice is walked in chunks of 32
 // rows; each chunk of X is loaded once (coalesced float4, double-buffered:
 // the next chunk's loads are issued before this chunk's MFMAs) and shared by
