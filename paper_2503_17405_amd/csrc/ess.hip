@@ -59,14 +59,16 @@ __global__ __launch_bounds__(256) void nu_gemm_simple_kernel(NuK<T> a)
 
 // ------------------------------------------------------------ FSM kernel
 // One wave = one chain, for one window of draws (ess_window).
-template <typename T, int EPL>
-__global__ __launch_bounds__(256) void ess_fsm_kernel(EssK<T> a)
+// FULL (D == 64 EPL) drops the element masks; it is a kernel of its own so
+// that each instantiation holds only one form of the loop (registers).
+template <typename T, int EPL, bool FULL>
+__device__ __forceinline__ void ess_fsm_body(const EssK<T>& a)
 {
     __shared__ unsigned long long s_sum;
     const int lane = threadIdx.x & 63;
     const int j = uni((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
     EssTally tl;
-    if (j < a.m) (void)ess_window<T, EPL>(a, j, lane, tl);
+    if (j < a.m) (void)ess_window_run<T, EPL, FULL>(a, j, lane, tl);
     // one atomic per block and counter
     const unsigned long long steps = block_sum_u64(tl.steps, &s_sum);
     if (threadIdx.x == 0 && steps) atomicAdd(&a.ctr[0], steps);
@@ -78,11 +80,23 @@ __global__ __launch_bounds__(256) void ess_fsm_kernel(EssK<T> a)
     if (threadIdx.x == 0 && left) atomicAdd(&a.ctr[3], left);
 }
 
+template <typename T, int EPL>
+__global__ __launch_bounds__(256) void ess_fsm_kernel(EssK<T> a)
+{
+    ess_fsm_body<T, EPL, false>(a);
+}
+
+template <typename T, int EPL>
+__global__ __launch_bounds__(256) void ess_fsm_full_kernel(EssK<T> a)
+{
+    ess_fsm_body<T, EPL, true>(a);
+}
+
 // ------------------------------------------------------------ synchronized
 // One draw of every chain (all chains at `draw`, at a draw boundary).
 // Chain j's draw `draw` (one wave); returns its evaluations, sets *rejected.
-template <typename T, int EPL>
-__device__ __forceinline__ int ess_sync_one(const EssK<T>& a, int j, int lane, uint32_t draw, uint32_t slot,
+template <typename T, int EPL, bool FULL>
+__device__ __forceinline__ int ess_sync_run(const EssK<T>& a, int j, int lane, uint32_t draw, uint32_t slot,
                                             bool* rejected)
 {
     T x[EPL], nu[EPL], xp[EPL], yv[EPL];
@@ -99,7 +113,7 @@ __device__ __forceinline__ int ess_sync_one(const EssK<T>& a, int j, int lane, u
     int evals = 0;
     T lp;
     for (;;) {
-        lp = uni(ess_propose_eval<T, EPL>(x, nu, xp, yv, theta, lane, a.D, a.target, a.inv2v));
+        lp = uni(ess_propose_eval<T, EPL, FULL>(x, nu, xp, yv, theta, lane, a.D, a.target, a.inv2v));
         ++evals;
         if (lp > logy || evals >= kEssMaxEvals) break;
         ess_shrink<T>(a.seed, (uint32_t)j, draw, evals, theta, tmin, tmax);
@@ -122,8 +136,8 @@ __device__ __forceinline__ int ess_sync_one(const EssK<T>& a, int j, int lane, u
     return evals;
 }
 
-template <typename T, int EPL>
-__global__ __launch_bounds__(256) void ess_sync_kernel(EssK<T> a, uint32_t draw, uint32_t slot)
+template <typename T, int EPL, bool FULL>
+__device__ __forceinline__ void ess_sync_body(const EssK<T>& a, uint32_t draw, uint32_t slot)
 {
     __shared__ unsigned long long s_sum;
     __shared__ int s_max;
@@ -131,7 +145,7 @@ __global__ __launch_bounds__(256) void ess_sync_kernel(EssK<T> a, uint32_t draw,
     const int j = uni((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
     int evals = 0;
     bool rejected = false;
-    if (j < a.m) evals = ess_sync_one<T, EPL>(a, j, lane, draw, slot, &rejected);
+    if (j < a.m) evals = ess_sync_run<T, EPL, FULL>(a, j, lane, draw, slot, &rejected);
     // one atomic per block and counter
     const unsigned long long steps = block_sum_u64((unsigned long long)evals, &s_sum);
     if (threadIdx.x == 0 && steps) atomicAdd(&a.ctr[0], steps);
@@ -141,10 +155,22 @@ __global__ __launch_bounds__(256) void ess_sync_kernel(EssK<T> a, uint32_t draw,
     if (threadIdx.x == 0) atomicMax(&a.maxN[draw], mx);
 }
 
+template <typename T, int EPL>
+__global__ __launch_bounds__(256) void ess_sync_kernel(EssK<T> a, uint32_t draw, uint32_t slot)
+{
+    ess_sync_body<T, EPL, false>(a, draw, slot);
+}
+
+template <typename T, int EPL>
+__global__ __launch_bounds__(256) void ess_sync_full_kernel(EssK<T> a, uint32_t draw, uint32_t slot)
+{
+    ess_sync_body<T, EPL, true>(a, draw, slot);
+}
+
 // The loop bodies a batched while loop runs for chain j after its own exit:
 // max_j N_j - N_j more proposals and log-likelihood evaluations, discarded.
-template <typename T, int EPL>
-__device__ __forceinline__ int ess_pad_one(const EssK<T>& a, int j, int lane, uint32_t draw, uint32_t slot)
+template <typename T, int EPL, bool FULL>
+__device__ __forceinline__ int ess_pad_run(const EssK<T>& a, int j, int lane, uint32_t draw, uint32_t slot)
 {
     const int nj_evals = uni(a.counts[(size_t)j * a.n + draw]);
     const int extra = uni(a.maxN[draw]) - nj_evals;
@@ -162,22 +188,34 @@ __device__ __forceinline__ int ess_pad_one(const EssK<T>& a, int j, int lane, ui
     for (int i = 0; i < extra; ++i) {
         const T theta = Pi<T>::two_pi * uniform<T>(a.seed, (uint32_t)j, draw, ROLE_ANGLE,
                                                     (uint32_t)(nj_evals + i));
-        sum += ess_propose_eval<T, EPL>(x, nu, xp, yv, theta, lane, a.D, a.target, a.inv2v);
+        sum += ess_propose_eval<T, EPL, FULL>(x, nu, xp, yv, theta, lane, a.D, a.target, a.inv2v);
     }
     if (lane == 0) a.sink[j] = sum;
     return extra;
 }
 
-template <typename T, int EPL>
-__global__ __launch_bounds__(256) void ess_pad_kernel(EssK<T> a, uint32_t draw, uint32_t slot)
+template <typename T, int EPL, bool FULL>
+__device__ __forceinline__ void ess_pad_body(const EssK<T>& a, uint32_t draw, uint32_t slot)
 {
     __shared__ unsigned long long s_sum;
     const int lane = threadIdx.x & 63;
     const int j = uni((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
     int extra = 0;
-    if (j < a.m) extra = ess_pad_one<T, EPL>(a, j, lane, draw, slot);
+    if (j < a.m) extra = ess_pad_run<T, EPL, FULL>(a, j, lane, draw, slot);
     const unsigned long long tot = block_sum_u64((unsigned long long)extra, &s_sum);
     if (threadIdx.x == 0 && tot) atomicAdd(&a.ctr[1], tot);
+}
+
+template <typename T, int EPL>
+__global__ __launch_bounds__(256) void ess_pad_kernel(EssK<T> a, uint32_t draw, uint32_t slot)
+{
+    ess_pad_body<T, EPL, false>(a, draw, slot);
+}
+
+template <typename T, int EPL>
+__global__ __launch_bounds__(256) void ess_pad_full_kernel(EssK<T> a, uint32_t draw, uint32_t slot)
+{
+    ess_pad_body<T, EPL, true>(a, draw, slot);
 }
 
 // ------------------------------------------------------------ host side
@@ -320,7 +358,11 @@ static hipError_t fsm_round_t(const JobDev& j, hipStream_t s)
 {
     EssK<T> a = ess_view<T>(j);
     const dim3 grid((j.m + 3) / 4), block(256);
-    FSMMC_EPL_DISPATCH(T, j.EPL, ess_fsm_kernel, grid, block, 0, s, a)
+    if (j.D == 64 * j.EPL) {
+        FSMMC_EPL_DISPATCH(T, j.EPL, ess_fsm_full_kernel, grid, block, 0, s, a)
+    } else {
+        FSMMC_EPL_DISPATCH(T, j.EPL, ess_fsm_kernel, grid, block, 0, s, a)
+    }
     return hipGetLastError();
 }
 
@@ -329,7 +371,11 @@ static hipError_t sync_draw_t(const JobDev& j, uint32_t draw, uint32_t slot, hip
 {
     EssK<T> a = ess_view<T>(j);
     const dim3 grid((j.m + 3) / 4), block(256);
-    FSMMC_EPL_DISPATCH(T, j.EPL, ess_sync_kernel, grid, block, 0, s, a, draw, slot)
+    if (j.D == 64 * j.EPL) {
+        FSMMC_EPL_DISPATCH(T, j.EPL, ess_sync_full_kernel, grid, block, 0, s, a, draw, slot)
+    } else {
+        FSMMC_EPL_DISPATCH(T, j.EPL, ess_sync_kernel, grid, block, 0, s, a, draw, slot)
+    }
     return hipGetLastError();
 }
 
@@ -338,7 +384,11 @@ static hipError_t pad_draw_t(const JobDev& j, uint32_t draw, uint32_t slot, hipS
 {
     EssK<T> a = ess_view<T>(j);
     const dim3 grid((j.m + 3) / 4), block(256);
-    FSMMC_EPL_DISPATCH(T, j.EPL, ess_pad_kernel, grid, block, 0, s, a, draw, slot)
+    if (j.D == 64 * j.EPL) {
+        FSMMC_EPL_DISPATCH(T, j.EPL, ess_pad_full_kernel, grid, block, 0, s, a, draw, slot)
+    } else {
+        FSMMC_EPL_DISPATCH(T, j.EPL, ess_pad_kernel, grid, block, 0, s, a, draw, slot)
+    }
     return hipGetLastError();
 }
 

@@ -377,7 +377,9 @@ __device__ __forceinline__ void nu_gemm_block(const NuK<float>& a, int col0)
 // FP32 logistic takes the log of the product of the factors 1 + e^-|f|: each
 // lies in (1, 2], so the product of at most 16 cannot overflow, and one log
 // replaces EPL of them (the transcendental units bound this loop).
-template <typename T, int EPL>
+// FULL: D == 64 EPL, every lane element exists and the masks drop out (the
+// same operations on the same values as the masked form).
+template <typename T, int EPL, bool FULL = false>
 __device__ __forceinline__ T ess_lane_loglik(const T (&f)[EPL], const T (&yv)[EPL], int lane, int D, int target,
                                              T inv2v)
 {
@@ -387,7 +389,7 @@ __device__ __forceinline__ T ess_lane_loglik(const T (&f)[EPL], const T (&yv)[EP
         for (int e = 0; e < EPL; ++e) {
             const T r = yv[e] - f[e];
             const T term = -(r * r) * inv2v;
-            acc += (e * 64 + lane < D) ? term : T(0);
+            acc += (FULL || e * 64 + lane < D) ? term : T(0);
         }
         return acc;
     }
@@ -396,7 +398,7 @@ __device__ __forceinline__ T ess_lane_loglik(const T (&f)[EPL], const T (&yv)[EP
         float prod = 1.0f;
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
-            const bool in = e * 64 + lane < D;
+            const bool in = FULL || e * 64 + lane < D;
             const float lin = yv[e] * f[e] - fmaxf(f[e], 0.0f);
             acc += in ? lin : 0.0f;
             prod *= in ? 1.0f + __expf(-fabsf(f[e])) : 1.0f;
@@ -406,7 +408,7 @@ __device__ __forceinline__ T ess_lane_loglik(const T (&f)[EPL], const T (&yv)[EP
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
             const T term = yv[e] * f[e] - M<T>::softplus(f[e]);
-            acc += (e * 64 + lane < D) ? term : T(0);
+            acc += (FULL || e * 64 + lane < D) ? term : T(0);
         }
         return acc;
     }
@@ -414,7 +416,7 @@ __device__ __forceinline__ T ess_lane_loglik(const T (&f)[EPL], const T (&yv)[EP
 
 // x' = x cos(theta) + nu sin(theta) and log L(x'), summed in a fixed order
 // (lane-local, then a wave butterfly); the result is wave-uniform.
-template <typename T, int EPL>
+template <typename T, int EPL, bool FULL = false>
 __device__ __forceinline__ T ess_propose_eval(const T (&x)[EPL], const T (&nu)[EPL], T (&xp)[EPL],
                                               const T (&yv)[EPL], T theta, int lane, int D, int target,
                                               T inv2v)
@@ -423,7 +425,7 @@ __device__ __forceinline__ T ess_propose_eval(const T (&x)[EPL], const T (&nu)[E
     M<T>::sincos_(theta, &s, &c);
 #pragma unroll
     for (int e = 0; e < EPL; ++e) xp[e] = M<T>::fma_(x[e], c, nu[e] * s);
-    return wave_sum(ess_lane_loglik<T, EPL>(xp, yv, lane, D, target, inv2v));
+    return wave_sum(ess_lane_loglik<T, EPL, FULL>(xp, yv, lane, D, target, inv2v));
 }
 
 // INIT: threshold log y = log L(x) + log u and the initial bracket.
@@ -472,8 +474,8 @@ struct EssTally {
 // window [t0, t0 + W), reached n draws, or spent its step budget.  Returns
 // the number of draws it emitted; the counter contributions go to tl (the
 // caller adds them to the job's counters).
-template <typename T, int EPL>
-__device__ __forceinline__ uint32_t ess_window(const EssK<T>& a, int j, int lane, EssTally& tl)
+template <typename T, int EPL, bool FULL>
+__device__ __forceinline__ uint32_t ess_window_run(const EssK<T>& a, int j, int lane, EssTally& tl)
 {
     j = uni(j);
     uint32_t t = uni(a.t[j]);
@@ -508,7 +510,7 @@ __device__ __forceinline__ uint32_t ess_window(const EssK<T>& a, int j, int lane
         } else {
             ess_shrink<T>(a.seed, (uint32_t)j, t, evals, theta, tmin, tmax);
         }
-        const T lp = uni(ess_propose_eval<T, EPL>(x, nu, xp, yv, theta, lane, a.D, a.target, a.inv2v));
+        const T lp = uni(ess_propose_eval<T, EPL, FULL>(x, nu, xp, yv, theta, lane, a.D, a.target, a.inv2v));
         ++evals;
         ++steps;
         --budget;
@@ -548,6 +550,13 @@ __device__ __forceinline__ uint32_t ess_window(const EssK<T>& a, int j, int lane
     tl.live = t < (uint32_t)a.n ? 1u : 0u;
     tl.budget_left = (tl.live && budget > 0) ? 1u : 0u;
     return t - t0;
+}
+
+template <typename T, int EPL>
+__device__ __forceinline__ uint32_t ess_window(const EssK<T>& a, int j, int lane, EssTally& tl)
+{
+    if (a.D == 64 * EPL) return ess_window_run<T, EPL, true>(a, j, lane, tl);
+    return ess_window_run<T, EPL, false>(a, j, lane, tl);
 }
 
 // Add one chain's tally to the job counters (lane 0 of its wave).
