@@ -11,8 +11,9 @@
 //      DRMH chains (one per lane) for `chunk` draws -- and runs the chains'
 //      FSM steps with the same device functions as the single-job kernels;
 //   4. nuts_steps NUTS runtime steps for every NUTS job: grouped transition
-//      (one wavefront per chain), per-job request compaction, grouped
-//      logistic-regression gradient tiles and grouped slice reductions;
+//      (one wavefront per chain; it adds up the row-slice partials of the
+//      gradient it consumes), per-job request compaction and grouped
+//      logistic-regression gradient tiles;
 //   5. batch_tally_kernel: per job, chains short of n and draws so far.
 // Every random number is keyed by (seed, chain, draw, role, sub) and every
 // reduction has a fixed order, so a job's draws do not depend on the batch,
@@ -53,7 +54,6 @@ struct BJob {
     DrK dr;
     NutsK nuts;
     GradK grad;
-    ReduceK red;
 };
 
 struct BItem {
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void batch_nuts_step_kernel(const BJob* jobs_i
 __global__ __launch_bounds__(1024) void batch_nuts_compact_kernel(const BJob* jobs, const int32_t* njobs)
 {
     const BJob& J = jobs[njobs[blockIdx.x]];
-    nuts_compact_block(J.nuts.req, J.m, 0, J.list, J.count, J.ctr);
+    nuts_compact_block<1024>(J.nuts.req, J.m, 0, J.list, J.count, J.ctr);
 }
 
 template <int DT>
@@ -185,16 +185,6 @@ __global__ __launch_bounds__(256) void batch_grad_kernel(const BJob* jobs_in, co
     const BGrad t = tiles[blockIdx.x];
     const GradK& a = *(const GradK*)&jobs[t.job].grad;
     logreg_grad_tile<DT>(a, t.ct, t.sl);
-}
-
-// Four listed chains per block (one per wavefront).
-template <int EPL>
-__global__ __launch_bounds__(256) void batch_reduce_kernel(const BJob* jobs_in, const BItem* items)
-{
-    const ConstBJob* jobs = (const ConstBJob*)jobs_in;
-    const BItem it = items[blockIdx.x];
-    const ReduceK& a = *(const ReduceK*)&jobs[it.job].red;
-    logreg_reduce_one<EPL>(a, it.first + (int)(threadIdx.x >> 6), threadIdx.x & 63);
 }
 
 // Block i: job i's chains short of n and its draws so far.
@@ -328,7 +318,7 @@ fsmmc_status rebuild(fsmmc_batch* b)
     std::vector<BJob> jv(nj);
     std::vector<std::pair<double, BItem>> items;
     std::vector<BTile> tiles[kTileSlots];
-    std::vector<BItem> nsteps[2], nred[2];
+    std::vector<BItem> nsteps[2];
     std::vector<BGrad> grads[2];
     std::vector<int32_t> njobs;
     for (int i = 0; i < nj; ++i) {
@@ -366,14 +356,12 @@ fsmmc_status rebuild(fsmmc_batch* b)
         } else {
             J.nuts = nuts_view(d, 0, 0);
             J.grad = grad_view(d, 0);
-            J.red = reduce_view(d, 0, (float*)d.Gres, (float*)d.Ures, d.Dp);
             J.list = d.list;
             J.count = d.count;
             if (!on) continue;
             J.cls = BC_NUTS;
             const int e = d.EPL == 1 ? 0 : 1;
             for (int c = 0; c < d.m; ++c) nsteps[e].push_back(BItem{i, c});
-            for (int c = 0; c < d.m; c += 4) nred[e].push_back(BItem{i, c});
             for (int ct = 0; ct * 64 < d.m; ++ct)
                 for (int sl = 0; sl < d.nslices; ++sl) grads[e].push_back(BGrad{i, ct, sl, 0});
             njobs.push_back(i);
@@ -395,11 +383,6 @@ fsmmc_status rebuild(fsmmc_batch* b)
     for (int e = 0; e < 2; ++e) {
         b->nstep_cnt[e] = (int)nsteps[e].size();
         nv.insert(nv.end(), nsteps[e].begin(), nsteps[e].end());
-    }
-    b->red_off = (int)nv.size();
-    for (int e = 0; e < 2; ++e) {
-        b->red_cnt[e] = (int)nred[e].size();
-        nv.insert(nv.end(), nred[e].begin(), nred[e].end());
     }
     std::vector<BGrad> gv;
     for (int e = 0; e < 2; ++e) {
@@ -466,13 +449,6 @@ fsmmc_status rebuild(fsmmc_batch* b)
         if (b->grad_cnt[1])
             hipLaunchKernelGGL(batch_grad_kernel<4>, dim3(b->grad_cnt[1]), dim3(256), 0, s, jobs,
                                (const BGrad*)b->d_grads + b->grad_cnt[0]);
-        chk();
-        const BItem* r1 = b->d_nitems + b->red_off;
-        if (b->red_cnt[0])
-            hipLaunchKernelGGL(batch_reduce_kernel<1>, dim3(b->red_cnt[0]), dim3(256), 0, s, jobs, r1);
-        if (b->red_cnt[1])
-            hipLaunchKernelGGL(batch_reduce_kernel<2>, dim3(b->red_cnt[1]), dim3(256), 0, s, jobs,
-                               r1 + b->red_cnt[0]);
         chk();
     }
     if (e == hipSuccess && nj > 0) {

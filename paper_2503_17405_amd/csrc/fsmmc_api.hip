@@ -373,8 +373,6 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
         ALLOC(d.US, m * 4);
         ALLOC(d.V, m * (size_t)d.nvec * Dp * 4);
         ALLOC(d.Thq, m * Dp * 4);
-        ALLOC(d.Gres, m * Dp * 4);
-        ALLOC(d.Ures, m * 4);
         ALLOC(d.req, m * 4);
         ALLOC(d.list, m * 4);
         ALLOC(d.count, 64);

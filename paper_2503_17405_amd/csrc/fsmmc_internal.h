@@ -65,8 +65,6 @@ struct JobDev {
     void* V = nullptr;         // m x nvec x Dp vector state
     int nvec = 0;
     void* Thq = nullptr;       // m x Dp positions whose gradient is requested
-    void* Gres = nullptr;      // m x Dp gradients returned
-    void* Ures = nullptr;      // m potentials returned
     int32_t* req = nullptr;    // m request flags
     int32_t* list = nullptr;   // m compacted requests
     int32_t* count = nullptr;  // 1

@@ -17,7 +17,8 @@
 //   3. X_chunk^T r on v_mfma_f32_16x16x4_f32 in 16-row tiles of d (D rounded
 //      up to 16): wave w owns chains 16 w .. +15 and every d tile, so partial
 //      gradients never need a cross-wave reduction.
-// Row slices are added in slice order by logreg_reduce_kernel; no float
+// Row slices are added in slice order (by the NUTS transition that consumes
+// the gradient, or by logreg_reduce_kernel for the starting points); no float
 // atomics, so every result is reproducible bit for bit.
 #include "logreg_device.h"
 
@@ -35,6 +36,7 @@ __global__ __launch_bounds__(256) void logreg_reduce_kernel(ReduceK a)
     logreg_reduce_one<EPL>(a, (int)(blockIdx.x * 4 + (threadIdx.x >> 6)), threadIdx.x & 63);
 }
 
+// Gout == nullptr: leave the row-slice partials for the consumer to add.
 static hipError_t grad_launch(const JobDev& j, int dense, float* Gout, float* Uout, int gstride, hipStream_t s)
 {
     const GradK g = grad_view(j, dense);
@@ -52,7 +54,7 @@ static hipError_t grad_launch(const JobDev& j, int dense, float* Gout, float* Uo
     }
 #undef FSMMC_GRAD_CASE
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !Gout) return e;
     const ReduceK r = reduce_view(j, dense, Gout, Uout, gstride);
     const dim3 rg((j.m + 3) / 4);
     if (j.Dp <= 64)
@@ -64,7 +66,7 @@ static hipError_t grad_launch(const JobDev& j, int dense, float* Gout, float* Uo
 
 hipError_t nuts_gradient(const JobDev& j, hipStream_t s)
 {
-    return grad_launch(j, 0, (float*)j.Gres, (float*)j.Ures, j.Dp, s);
+    return grad_launch(j, 0, nullptr, nullptr, 0, s);
 }
 
 hipError_t nuts_gradient_dense(const JobDev& j, int ncols, float* Gout, float* Uout, int gstride, hipStream_t s)

@@ -48,7 +48,7 @@ struct fsmmc_batch {
     size_t cap_items = 0;
     fsmmc::BTile* d_tiles = nullptr;  // ellipse GEMM tiles
     size_t cap_tiles = 0;
-    fsmmc::BItem* d_nitems = nullptr;  // NUTS chains (EPL 1, then EPL 2), then reduce groups
+    fsmmc::BItem* d_nitems = nullptr;  // NUTS chains (EPL 1, then EPL 2)
     size_t cap_nitems = 0;
     fsmmc::BGrad* d_grads = nullptr;  // NUTS gradient tiles (Dp 64, then Dp 128)
     size_t cap_grads = 0;
@@ -59,7 +59,7 @@ struct fsmmc_batch {
     size_t cap_stat = 0;
     int n_items = 0, fsm_blocks = 0;
     int tile_off[fsmmc::kTileSlots] = {0}, tile_cnt[fsmmc::kTileSlots] = {0};
-    int nstep_cnt[2] = {0, 0}, red_off = 0, red_cnt[2] = {0, 0}, grad_cnt[2] = {0, 0}, n_nuts = 0;
+    int nstep_cnt[2] = {0, 0}, grad_cnt[2] = {0, 0}, n_nuts = 0;
     hipGraphExec_t exec = nullptr;
     bool dirty = true;
     int pending_k = 0;  // replays launched and not yet collected

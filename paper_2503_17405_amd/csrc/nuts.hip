@@ -4,19 +4,19 @@
 // and an inner integration loop), for Bayesian logistic regression.
 //
 // One runtime step for every chain:
-//   1. nuts_step_kernel (one wavefront per chain): finish the leapfrog whose
-//      gradient just arrived (second half-kick, multinomial leaf choice,
-//      U-turn checkpoints), then run the cheap states back to back (CHECK,
-//      DONE, INIT, DOUBLE) until the chain needs the next gradient, and
-//      issue the first half of that leapfrog (Appendix, Alg. "bundled step
-//      as input to amortized step").
+//   1. nuts_step_kernel (one wavefront per chain): add up the row-slice
+//      partials of the gradient that just arrived, in slice order
+//      (grad U = theta - X^T r, U = |theta|^2 / 2 - loglik), finish that
+//      leapfrog (second half-kick, multinomial leaf choice, U-turn
+//      checkpoints), then run the cheap states back to back (CHECK, DONE,
+//      INIT, DOUBLE) until the chain needs the next gradient, and issue the
+//      first half of that leapfrog (Appendix, Alg. "bundled step as input to
+//      amortized step").
 //   2. nuts_compact_kernel: list of chains that asked for a gradient, in
 //      chain order.
 //   3. logreg_grad_kernel: eta = X Theta, r = y - sigmoid(eta), X^T r and
 //      the log-likelihood, fused on FP32 MFMA for a tile of 64 listed chains
 //      and a slice of rows; eta never leaves registers.
-//   4. logreg_reduce_kernel: sums the row-slice partials in a fixed order:
-//      grad U = theta - X^T r, U = |theta|^2 / 2 - loglik.
 // The synchronized runtime uses the same kernels; a chain that finishes a
 // draw waits until every chain has finished it (device-side barrier), and in
 // vmap mode the gradient phase then covers every chain.
@@ -38,29 +38,30 @@ __global__ __launch_bounds__(256) void nuts_step_kernel(NutsK a)
     }
     int bits = 0;
     if (c < a.m) bits = nuts_chain_step<EPL>(a, c, lane);
-    if (a.mode == 0) return;  // the FSM runtime stops when no chain requests a gradient
-    // synchronized runtimes: chains alive / still inside their draw, one atomic per block
-    __shared__ unsigned s_alive, s_indraw;
-    if (threadIdx.x == 0) {
-        s_alive = 0;
-        s_indraw = 0;
-    }
-    __syncthreads();
-    if (lane == 0 && bits) {
-        atomicAdd(&s_alive, (bits & NC_ALIVE) ? 1u : 0u);
-        atomicAdd(&s_indraw, (bits & NC_INDRAW) ? 1u : 0u);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if (s_alive) atomicAdd(&a.wctr[3 + a.step % 3], s_alive);
-        if (s_indraw) atomicAdd(&a.wctr[a.step % 3], s_indraw);
+    if (a.mode != 0) {
+        // synchronized runtimes: chains alive / still inside their draw, one atomic per block
+        __shared__ unsigned s_alive, s_indraw;
+        if (threadIdx.x == 0) {
+            s_alive = 0;
+            s_indraw = 0;
+        }
+        __syncthreads();
+        if (lane == 0 && bits) {
+            atomicAdd(&s_alive, (bits & NC_ALIVE) ? 1u : 0u);
+            atomicAdd(&s_indraw, (bits & NC_INDRAW) ? 1u : 0u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (s_alive) atomicAdd(&a.wctr[3 + a.step % 3], s_alive);
+            if (s_indraw) atomicAdd(&a.wctr[a.step % 3], s_indraw);
+        }
     }
 }
 
 __global__ __launch_bounds__(1024) void nuts_compact_kernel(const int32_t* req, int m, int vmap, int32_t* list,
                                                             int32_t* count, unsigned long long* ctr)
 {
-    nuts_compact_block(req, m, vmap, list, count, ctr);
+    nuts_compact_block<1024>(req, m, vmap, list, count, ctr);
 }
 
 // Default start: theta0 ~ N(0, I) from the INIT stream (into both buffers).

@@ -33,8 +33,9 @@ struct NutsK {
     float *H0, *W, *Ws, *UP, *US;
     float* V;  // [chain][nvec][Dp]
     float* Thq;
-    const float* Gres;
-    const float* Ures;
+    const float* Gpart;  // gradient row-slice partials: [slice][chain][Dp]
+    const float* Upart;  // log-likelihood row-slice partials: [slice][chain]
+    int nslices;
     int32_t* req;
     float* out;
     int32_t* counts;
@@ -82,15 +83,27 @@ __device__ __forceinline__ int nuts_chain_step(const NutsK& a, int c, int lane)
     if (fl & NF_PENDING) {
         const int eth = v > 0 ? V_THR : V_THL, ep = v > 0 ? V_PR : V_PL, eg = v > 0 ? V_GR : V_GL;
         const float vhe = (float)v * he;
-        // independent loads issued together: gradient, half-step momentum, new edge position, rho_sub
+        // independent loads issued together: half-step momentum, new edge position, rho_sub
         WaveVec<EPL> g, p, ph, th, rs;
-        g.load(a.Gres + (size_t)c * a.Dp, lane);
         ph.load(vec(V_PH), lane);
         th.load(vec(eth), lane);
         rs.load(vec(V_RHOS), lane);
+        // the gradient's row-slice partials, added in slice order:
+        // grad U = theta - sum_s X_s^T r_s,  U = |theta|^2 / 2 - sum_s loglik_s
+        float ll = 0.0f;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) g.r[e] = 0.0f;
+        for (int s = 0; s < a.nslices; ++s) {
+            const float* gp = a.Gpart + ((size_t)s * a.m + c) * a.Dp;
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) g.r[e] += gp[e * 64 + lane];
+            ll += a.Upart[(size_t)s * a.m + c];
+        }
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) g.r[e] = th.r[e] - g.r[e];
+        const float Un = uni(0.5f * wdot(th, th) - ll);
 #pragma unroll
         for (int e = 0; e < EPL; ++e) p.r[e] = ph.r[e] - vhe * g.r[e];
-        const float Un = uni(a.Ures[c]);
         ++nleap;
         const float w = H0 - (Un + 0.5f * wdot(p, p));
         p.store(vec(ep), lane);
@@ -286,27 +299,28 @@ __device__ __forceinline__ int nuts_chain_step(const NutsK& a, int c, int lane)
 }
 
 // Chains of one job that asked for a gradient, in chain order (one block of
-// 1024 threads).  In vmap mode a gradient phase that anyone needs covers
+// NT threads).  In vmap mode a gradient phase that anyone needs covers
 // every chain.
+template <int NT>
 __device__ __forceinline__ void nuts_compact_block(const int32_t* req, int m, int vmap, int32_t* list,
                                                    int32_t* count, unsigned long long* ctr)
 {
-    __shared__ int part[1024];
+    __shared__ int part[NT];
     const int tid = threadIdx.x;
-    const int per = (m + 1023) / 1024;
+    const int per = (m + NT - 1) / NT;
     const int b = tid * per, e = min(m, b + per);
     int local = 0;
     for (int i = b; i < e; ++i) local += req[i] != 0;
     part[tid] = local;
     __syncthreads();
     // inclusive scan (Hillis-Steele)
-    for (int o = 1; o < 1024; o <<= 1) {
+    for (int o = 1; o < NT; o <<= 1) {
         const int add = tid >= o ? part[tid - o] : 0;
         __syncthreads();
         part[tid] += add;
         __syncthreads();
     }
-    const int total = part[1023];
+    const int total = part[NT - 1];
     if (vmap) {
         if (tid == 0) {
             *count = total > 0 ? m : 0;
@@ -316,7 +330,7 @@ __device__ __forceinline__ void nuts_compact_block(const int32_t* req, int m, in
             }
         }
         if (total > 0)
-            for (int i = tid; i < m; i += 1024) list[i] = i;
+            for (int i = tid; i < m; i += NT) list[i] = i;
         return;
     }
     int pos = part[tid] - local;
@@ -359,8 +373,9 @@ inline NutsK nuts_view(const JobDev& j, int mode, uint32_t step)
     a.US = (float*)j.US;
     a.V = (float*)j.V;
     a.Thq = (float*)j.Thq;
-    a.Gres = (const float*)j.Gres;
-    a.Ures = (const float*)j.Ures;
+    a.Gpart = (const float*)j.Gpart;
+    a.Upart = (const float*)j.Upart;
+    a.nslices = j.nslices;
     a.req = j.req;
     a.out = (float*)j.out;
     a.counts = j.counts;
