@@ -129,7 +129,7 @@ def test_ess_fp32_d1024_oracle_parity(F, ctx):
     assert nflip <= m // 4
 
 
-@pytest.mark.parametrize("D", [1, 17, 100, 333, 700])
+@pytest.mark.parametrize("D", [1, 17, 100, 333, 700, 769, 1000])
 def test_ess_ragged_dims_oracle_parity(F, ctx, D):
     w = inputs.gp_logistic(dim=D, lengthscale=0.1, jitter=1e-5, seed=D)
     m, n = 37, 40
