@@ -226,8 +226,9 @@ fsmmc_status fsmmc_job_free(fsmmc_job* job);
  *     DRMH chains (one per lane) for `dr_chunk` draws -- and run the chains'
  *     FSM steps (Sec. 3.2, Alg. "Vectorized FSM MCMC algorithm") without
  *     waiting for any other chain or job;
- *   - `nuts_steps` NUTS runtime steps of every NUTS job: grouped transition,
- *     per-job request compaction, grouped gradient tiles and reductions.
+ *   - `nuts_steps` NUTS runtime steps of every NUTS job: grouped transition
+ *     (which adds up the gradient's row-slice partials it consumes), per-job
+ *     request compaction and grouped gradient tiles.
  * Chains of a job never synchronise with other jobs, and a job's draws are
  * bit-identical to running it alone with fsmmc_step_fsm.  While a job
  * belongs to a batch, the per-job stepping calls and fsmmc_job_free return
