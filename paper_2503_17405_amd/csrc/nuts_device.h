@@ -299,28 +299,36 @@ __device__ __forceinline__ int nuts_chain_step(const NutsK& a, int c, int lane)
 }
 
 // Chains of one job that asked for a gradient, in chain order (one block of
-// NT threads).  In vmap mode a gradient phase that anyone needs covers
-// every chain.
+// NT threads).  The flags are read in coalesced rounds of NT chains; within a
+// round a wave places its requesters by ballot and bit count, and the waves'
+// offsets come from their counts in LDS.  In vmap mode a gradient phase that
+// anyone needs covers every chain.
 template <int NT>
 __device__ __forceinline__ void nuts_compact_block(const int32_t* req, int m, int vmap, int32_t* list,
                                                    int32_t* count, unsigned long long* ctr)
 {
-    __shared__ int part[NT];
-    const int tid = threadIdx.x;
-    const int per = (m + NT - 1) / NT;
-    const int b = tid * per, e = min(m, b + per);
-    int local = 0;
-    for (int i = b; i < e; ++i) local += req[i] != 0;
-    part[tid] = local;
-    __syncthreads();
-    // inclusive scan (Hillis-Steele)
-    for (int o = 1; o < NT; o <<= 1) {
-        const int add = tid >= o ? part[tid - o] : 0;
+    constexpr int NW = NT / 64;
+    __shared__ int wsum[NW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const unsigned long long below_mask = (1ull << lane) - 1ull;
+    int total = 0;  // requesters in the rounds before this one (the same in every thread)
+    for (int r0 = 0; r0 < m; r0 += NT) {
+        const int i = r0 + tid;
+        const bool f = i < m && req[i] != 0;
+        const unsigned long long bal = __ballot(f);
+        if (lane == 0) wsum[wave] = __popcll(bal);
         __syncthreads();
-        part[tid] += add;
-        __syncthreads();
+        int woff = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int v = wsum[w];
+            woff += w < wave ? v : 0;
+            tot += v;
+        }
+        if (f && !vmap) list[total + woff + __popcll(bal & below_mask)] = i;
+        total += tot;
+        __syncthreads();  // wsum is rewritten by the next round
     }
-    const int total = part[NT - 1];
     if (vmap) {
         if (tid == 0) {
             *count = total > 0 ? m : 0;
@@ -333,9 +341,6 @@ __device__ __forceinline__ void nuts_compact_block(const int32_t* req, int m, in
             for (int i = tid; i < m; i += NT) list[i] = i;
         return;
     }
-    int pos = part[tid] - local;
-    for (int i = b; i < e; ++i)
-        if (req[i]) list[pos++] = i;
     if (tid == 0) {
         *count = total;
         if (total > 0) atomicAdd(&ctr[0], (unsigned long long)total);
