@@ -14,7 +14,9 @@ Reported beside it, on the same box and run:
     compacted variant), the FSM/synchronized speed-ups and bit-exactness;
   * NUTS on Bayesian logistic regression (N = 10000, D = 100, step 0.05,
     depth 10, Laplace starts), 8192 chains x 1000 draws, FSM vs synchronized;
-  * R(m) of each job estimated from its own loop counts;
+  * R(m) of each job estimated from its own loop counts, chain transitions
+    per second, and effective samples per second (multi-chain ESS of the
+    first coordinates on a subsample of the chains);
   * batching: 32 GP-logistic ESS targets of uneven dim / chains / draws plus a
     65536-chain D=10 funnel under 3-stage delayed rejection, in one batch
     (one graph replay per round, autotuned), against the same jobs run one
@@ -79,6 +81,19 @@ def checksum(out, m_chunk=256):
     return s
 
 
+def ess_report(out, seconds, chains=256, coords=4):
+    """Effective samples per second of the first `coords` coordinates, from the
+    draws of the first `chains` chains (chains are i.i.d., so the sum over all
+    chains scales by m / chains); the minimum over the coordinates is reported."""
+    from paper_2503_17405_amd import diagnostics as Dx
+    m = out.shape[0]
+    c = min(chains, m)
+    sub = out[:c, :, :coords].double().cpu().numpy()
+    e = Dx.ess(sub) * (m / c)
+    return dict(ess_per_s=float(e.min() / seconds), ess_min=float(e.min()), ess_mean=float(e.mean()),
+                sample="chains 0..%d, coordinates 0..%d, all draws" % (c - 1, coords - 1))
+
+
 def timed_jobs(make, run, steps, warmup):
     import torch
     for i in range(warmup):
@@ -102,7 +117,7 @@ def timed_jobs(make, run, steps, warmup):
 def bench_ess(F, ctx, args):
     import torch
 
-    from oracle import diagnostics as Dg
+    from paper_2503_17405_amd import diagnostics as Dx
     from paper_2503_17405_amd import inputs
     m, n, D = args.chains, args.draws, 1024
     w = inputs.gp_logistic(dim=D, lengthscale=0.05, jitter=1e-5, seed=2001)
@@ -120,9 +135,11 @@ def bench_ess(F, ctx, args):
     job.free()
     ref = checksum(out)
     res = dict(seconds=t_fsm, draws_per_s=m * n / t_fsm, steps=st["steps"],
+               transitions_per_s=st["steps"] / t_fsm,
                kernel_ms=st["kernel_ms"], kernel_launches=st["kernel_launches"],
                mean_loop=float(counts.mean()), mean_max_loop=float(counts.max(axis=0).mean()),
-               R_hat_m=Dg.r_hat_m(counts, m))
+               R_hat_m=Dx.r_of_m(counts, m))
+    res["effective"] = ess_report(out, t_fsm)
     g_ms, g_n = st["kernel_ms"][0], st["kernel_launches"][0]
     flops = float(m) * n * D * (D + 1)
     # in the job, each window's GEMM shares the chip with the previous window's FSM kernel
@@ -161,7 +178,7 @@ def bench_nuts(F, ctx, args):
     import numpy as np
     import torch
 
-    from oracle import diagnostics as Dg
+    from paper_2503_17405_amd import diagnostics as Dx
     from paper_2503_17405_amd import inputs
     m, n, N, D = args.nuts_chains, args.nuts_draws, 10000, 100
     d = inputs.logreg(n_data=N, dim=D, seed=3001)
@@ -180,12 +197,14 @@ def bench_nuts(F, ctx, args):
     job.free()
     ref = checksum(out)
     res = dict(seconds=t_fsm, draws_per_s=m * n / t_fsm, steps=st["steps"],
+               transitions_per_s=st["steps"] / t_fsm,
                kernel_ms=st["kernel_ms"], kernel_launches=st["kernel_launches"],
                mean_loop=float(counts.mean()), mean_max_loop=float(counts.max(axis=0).mean()),
-               R_hat_m=Dg.r_hat_m(counts, m), divergent_free=bool(np.isfinite(counts).all()))
+               R_hat_m=Dx.r_of_m(counts, m), divergent_free=bool(np.isfinite(counts).all()))
+    res["effective"] = ess_report(out, t_fsm)
     g_ms = st["kernel_ms"][0]
     flops = 4.0 * N * D * st["steps"]  # X Theta and X^T r per requested gradient
-    res["gradient"] = dict(kernel="logreg_grad_kernel<4> + logreg_reduce_kernel", ms=g_ms,
+    res["gradient"] = dict(kernel="logreg_grad_kernel<4>", ms=g_ms,
                            launches=st["kernel_launches"][0],
                            tflops=flops / (g_ms * 1e-3) / 1e12, flop_per_gradient=4 * N * D)
     sync = {}
