@@ -108,17 +108,17 @@ __device__ __forceinline__ int ess_sync_run(const EssK<T>& a, int j, int lane, u
         yv[e] = a.y[e * 64 + lane];
         nu[e] = nj[e * 64 + lane];
     }
-    T lx = uni(a.lx[j]), logy, theta, tmin, tmax;
-    ess_begin<T>(a.seed, (uint32_t)j, draw, lx, logy, theta, tmin, tmax);
+    T lx = uni(a.lx[j]), logu, theta, tmin, tmax;
+    ess_begin<T>(a.seed, (uint32_t)j, draw, logu, theta, tmin, tmax);
     int evals = 0;
     T lp;
     for (;;) {
         lp = uni(ess_propose_eval<T, EPL, FULL>(x, nu, xp, yv, theta, lane, a.D, a.target, a.inv2v));
         ++evals;
-        if (lp > logy || evals >= kEssMaxEvals) break;
+        if (lp - lx > logu || evals >= kEssMaxEvals) break;
         ess_shrink<T>(a.seed, (uint32_t)j, draw, evals, theta, tmin, tmax);
     }
-    const bool accept = lp > logy;
+    const bool accept = lp - lx > logu;
     if (accept) {
 #pragma unroll
         for (int e = 0; e < EPL; ++e) x[e] = xp[e];

@@ -37,7 +37,7 @@ struct EssK {
     uint32_t* t;
     int32_t* evals;
     int64_t* budget;
-    T *theta, *tmin, *tmax, *logy, *lx, *x, *out;
+    T *theta, *tmin, *tmax, *logu, *lx, *x, *out;
     int32_t* counts;
     unsigned long long* ctr;
     int32_t* maxN;
@@ -428,12 +428,17 @@ __device__ __forceinline__ T ess_propose_eval(const T (&x)[EPL], const T (&nu)[E
     return wave_sum(ess_lane_loglik<T, EPL, FULL>(xp, yv, lane, D, target, inv2v));
 }
 
-// INIT: threshold log y = log L(x) + log u and the initial bracket.
+// INIT: the slice level log y = log L(x) + log u, kept as log u, and the
+// initial bracket.  A proposal is accepted when log L(x') - log L(x) > log u,
+// which is log L(x') > log y in exact arithmetic; in floating point it still
+// accepts x' == x (the limit of a collapsing bracket), whereas log L(x) + log u
+// rounds to log L(x) when |log u| is below the rounding of log L(x) and then
+// no proposal near x would ever pass.
 template <typename T>
-__device__ __forceinline__ void ess_begin(uint64_t seed, uint32_t chain, uint32_t draw, T lx, T& logy,
-                                          T& theta, T& tmin, T& tmax)
+__device__ __forceinline__ void ess_begin(uint64_t seed, uint32_t chain, uint32_t draw, T& logu, T& theta,
+                                          T& tmin, T& tmax)
 {
-    logy = lx + M<T>::log_(uniform<T>(seed, chain, draw, ROLE_THRESH, 0));
+    logu = M<T>::log_(uniform<T>(seed, chain, draw, ROLE_THRESH, 0));
     theta = Pi<T>::two_pi * uniform<T>(seed, chain, draw, ROLE_ANGLE, 0);
     tmin = theta - Pi<T>::two_pi;
     tmax = theta;
@@ -483,7 +488,7 @@ __device__ __forceinline__ uint32_t ess_window_run(const EssK<T>& a, int j, int 
     const uint32_t t0 = t;
     const uint32_t wend = min(t0 + (uint32_t)a.W, (uint32_t)a.n);
     int k = uni(a.k[j]), evals = uni(a.evals[j]);
-    T theta = uni(a.theta[j]), tmin = uni(a.tmin[j]), tmax = uni(a.tmax[j]), logy = uni(a.logy[j]),
+    T theta = uni(a.theta[j]), tmin = uni(a.tmin[j]), tmax = uni(a.tmax[j]), logu = uni(a.logu[j]),
       lx = uni(a.lx[j]);
     int64_t budget = uni((int64_t)a.budget[j]);
 
@@ -505,7 +510,7 @@ __device__ __forceinline__ uint32_t ess_window_run(const EssK<T>& a, int j, int 
             have_nu = true;
         }
         if (k == 1) {
-            ess_begin<T>(a.seed, (uint32_t)j, t, lx, logy, theta, tmin, tmax);
+            ess_begin<T>(a.seed, (uint32_t)j, t, logu, theta, tmin, tmax);
             evals = 0;
         } else {
             ess_shrink<T>(a.seed, (uint32_t)j, t, evals, theta, tmin, tmax);
@@ -514,7 +519,7 @@ __device__ __forceinline__ uint32_t ess_window_run(const EssK<T>& a, int j, int 
         ++evals;
         ++steps;
         --budget;
-        const bool accept = lp > logy;
+        const bool accept = lp - lx > logu;
         if (accept || evals >= kEssMaxEvals) {
             if (accept) {
 #pragma unroll
@@ -541,7 +546,7 @@ __device__ __forceinline__ uint32_t ess_window_run(const EssK<T>& a, int j, int 
         a.theta[j] = theta;
         a.tmin[j] = tmin;
         a.tmax[j] = tmax;
-        a.logy[j] = logy;
+        a.logu[j] = logu;
         a.lx[j] = lx;
         a.budget[j] = budget;
     }
@@ -592,7 +597,7 @@ inline EssK<T> ess_view(const JobDev& j)
     a.theta = (T*)j.theta;
     a.tmin = (T*)j.tmin;
     a.tmax = (T*)j.tmax;
-    a.logy = (T*)j.logy;
+    a.logu = (T*)j.logu;
     a.lx = (T*)j.lx;
     a.x = (T*)j.x;
     a.out = (T*)j.out;

@@ -296,7 +296,7 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
         ALLOC(d.theta, m * es);
         ALLOC(d.tmin, m * es);
         ALLOC(d.tmax, m * es);
-        ALLOC(d.logy, m * es);
+        ALLOC(d.logu, m * es);
         ALLOC(d.sink, m * es);
         ALLOC(d.maxN, (size_t)d.n * 4);
         ALLOC(d.L, Dp * Dp * es);

@@ -46,7 +46,7 @@ struct JobDev {
     void* theta = nullptr;
     void* tmin = nullptr;
     void* tmax = nullptr;
-    void* logy = nullptr;
+    void* logu = nullptr;
     void* nu = nullptr;  // 2 x m x Wcap x Dp ellipse directions (double-buffered windows)
     int W = 0;           // draws per window (<= Wcap)
     int Wcap = 0;        // draws one direction buffer holds per chain

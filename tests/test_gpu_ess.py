@@ -129,6 +129,41 @@ def test_ess_fp32_d1024_oracle_parity(F, ctx):
     assert nflip <= m // 4
 
 
+def test_ess_c2_full_size_sampled_chains_oracle_parity(F, ctx):
+    """The benchmark's job itself (8192 chains x 2000 draws, D = 1024, default
+    window, pipelined GEMM): sampled chains against the oracle run for those
+    chain indices alone, over their first 100 draws; flips must be near-ties."""
+    w = inputs.gp_logistic(dim=1024, lengthscale=0.05, jitter=1e-5, seed=2001)
+    m, n, D, seed, first = 8192, 2000, 1024, 2002, 100
+    out = torch.empty((m, n, D), dtype=torch.float32, device="cuda")
+    job = F.Job(ctx, F.gp_target(_dev(w["L"], torch.float32), _dev(w["y"], torch.float32)),
+                F.ess_sampler(F.F32), m, n, seed, out=out)
+    try:
+        assert job.step_fsm(0)
+        C = job.counts()
+        st = job.stats()
+    finally:
+        job.free()
+    idx = [0, 1, 4095, 4096, 8191] + sorted(int(i) for i in np.random.default_rng(11).choice(m, 5, replace=False))
+    S = out[idx, :first].cpu().numpy()
+    del out
+    torch.cuda.empty_cache()
+    assert st["chains_done"] == m and st["guard_trips"] == 0 and st["draws"] == m * n
+    tg = O.gp_target(w["y"])
+    R, RC, guards = O.run_chains(tg, O.ess_sampler(w["L"]), seed, idx, first)
+    assert guards == 0
+    err, flips = parity.compare_draws(S, R, C[idx], RC, first=first)
+    bad = 0
+    for k in np.nonzero(flips >= 0)[0]:
+        j, t = idx[k], int(flips[k])
+        x_prev = R[k, t - 1] if t > 0 else O.ess_init(w["L"], seed, j)
+        margin, terms = parity.ess_flip_margin(tg, w["L"], seed, j, t, x_prev, int(C[j, t]), int(RC[k, t]))
+        bad += not parity.is_near_tie(margin, terms)
+    print("C2 full size, chains %s: max rel err %.3g, flips %d, not near-tie %d"
+          % (idx, err, int((flips >= 0).sum()), bad))
+    assert err <= 1e-4 and bad == 0
+
+
 @pytest.mark.parametrize("D", [1, 17, 100, 333, 700, 769, 1000])
 def test_ess_ragged_dims_oracle_parity(F, ctx, D):
     w = inputs.gp_logistic(dim=D, lengthscale=0.1, jitter=1e-5, seed=D)

@@ -131,6 +131,35 @@ def test_nuts_logreg_c3_shape_parity(F, ctx):
     assert err <= 1e-4 and bad == 0
 
 
+def test_nuts_c3_full_size_sampled_chains_oracle_parity(F, ctx):
+    """The benchmark's NUTS job itself (8192 chains x 1000 draws, N = 10000,
+    D = 100): sampled chains against the oracle run for those chains alone,
+    over their first 25 draws; flips must be near-ties of the oracle."""
+    d = inputs.logreg(n_data=10000, dim=100, seed=3001)
+    m, n, seed, eps, J, first = 8192, 1000, 3003, 0.05, 10, 25
+    lap = inputs.logreg_laplace(d["X"], d["y"], m, seed=3002)
+    out = torch.empty((m, n, 100), dtype=torch.float32, device="cuda")
+    _, C, st = gpu_nuts(F, ctx, d, m, n, seed, eps, J, x0=lap["x0"], out=out)
+    idx = [0, 1, 4095, 8191] + sorted(int(i) for i in np.random.default_rng(13).choice(m, 4, replace=False))
+    S = out[idx, :first].cpu().numpy()
+    del out
+    torch.cuda.empty_cache()
+    assert st["chains_done"] == m and st["draws"] == m * n
+    tg = O.logreg_target(d["X"].astype(np.float64), d["y"])
+    x0 = lap["x0"][idx]
+    R, RC, _ = O.run_chains(tg, O.nuts_sampler(eps, J), seed, idx, first, x0=x0)
+    err, flips = parity.compare_draws(S, R, C[idx], RC, first=first)
+    bad = 0
+    for k in np.nonzero(flips >= 0)[0]:
+        j, t = idx[k], int(flips[k])
+        xp = R[k, t - 1] if t > 0 else x0[k]
+        near, _ = parity.nuts_flip_near_tie(tg, eps, J, seed, j, t, xp)
+        bad += not near
+    print("C3 full size, chains %s: max rel err %.3g, flips %d, not near-tie %d"
+          % (idx, err, int((flips >= 0).sum()), bad))
+    assert err <= 1e-4 and bad == 0
+
+
 def test_nuts_depth_one_and_default_init(F, ctx):
     d = inputs.logreg(n_data=300, dim=4, seed=5)
     m, n, seed = 9, 40, 6
