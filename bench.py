@@ -126,8 +126,13 @@ def bench_ess(F, ctx, args):
     y = torch.tensor(w["y"], dtype=torch.float32, device="cuda")
     out = torch.empty((m, n, D), dtype=torch.float32, device="cuda")
     target, sampler = F.gp_target(L, y), F.ess_sampler(F.F32)
-    make = lambda: F.Job(ctx, target, sampler, m, n, seed, out=out, window=args.window, timing=True)
+    def make(timing=True):
+        return F.Job(ctx, target, sampler, m, n, seed, out=out, window=args.window, timing=timing)
 
+    # the FSM job is timed with HIP events around its launches (63 windows: the
+    # live roofline of the GEMM); the synchronized baselines issue thousands of
+    # launches, so they are timed without events and their kernel breakdown
+    # comes from one more run with events
     log("ESS FSM")
     t_fsm, job = timed_jobs(make, lambda j: j.step_fsm(0), args.steps, args.warmup)
     st = job.stats()
@@ -162,12 +167,18 @@ def bench_ess(F, ctx, args):
     if not args.no_sync:
         for name, mode in (("vmap", F.SYNC_VMAP), ("compact", F.SYNC_COMPACT)):
             log("ESS sync %s" % name)
-            dt, job = timed_jobs(make, lambda j, mode=mode: j.step_synchronized(n, mode), args.sync_steps, 0)
+            dt, job = timed_jobs(lambda: make(False), lambda j, mode=mode: j.step_synchronized(n, mode),
+                                 args.sync_steps, 0)
             s2 = job.stats()
             job.free()
+            exact = bool(checksum(out) == ref)
+            job = make(True)
+            job.step_synchronized(n, mode)
+            kms = job.stats()["kernel_ms"]
+            job.free()
             sync[name] = dict(seconds=dt, draws_per_s=m * n / dt, steps=s2["steps"],
-                              padded_steps=s2["padded_steps"], kernel_ms=s2["kernel_ms"],
-                              bit_exact_vs_fsm=bool(checksum(out) == ref), speedup_fsm=dt / t_fsm)
+                              padded_steps=s2["padded_steps"], kernel_ms=kms,
+                              bit_exact_vs_fsm=exact, speedup_fsm=dt / t_fsm)
     res["sync"] = sync
     del out
     torch.cuda.empty_cache()
@@ -189,13 +200,22 @@ def bench_nuts(F, ctx, args):
     out = torch.empty((m, n, D), dtype=torch.float32, device="cuda")
     target, sampler = F.logreg_target(X, y), F.nuts_sampler(0.05, 10)
     seed = 3003
-    make = lambda: F.Job(ctx, target, sampler, m, n, seed, x0=x0, out=out, timing=True)
+    def make(timing=False):
+        return F.Job(ctx, target, sampler, m, n, seed, x0=x0, out=out, timing=timing)
+
+    # timed without per-launch events (thousands of steps); the kernel
+    # breakdown comes from one more FSM run with events
     log("NUTS FSM")
     t_fsm, job = timed_jobs(make, lambda j: j.step_fsm(0), args.nuts_steps, args.nuts_warmup)
     st = job.stats()
     counts = job.counts()
     job.free()
     ref = checksum(out)
+    job = make(True)
+    job.step_fsm(0)
+    st_t = job.stats()
+    job.free()
+    st["kernel_ms"], st["kernel_launches"] = st_t["kernel_ms"], st_t["kernel_launches"]
     res = dict(seconds=t_fsm, draws_per_s=m * n / t_fsm, steps=st["steps"],
                transitions_per_s=st["steps"] / t_fsm,
                kernel_ms=st["kernel_ms"], kernel_launches=st["kernel_launches"],
@@ -215,7 +235,7 @@ def bench_nuts(F, ctx, args):
             s2 = job.stats()
             job.free()
             sync[name] = dict(seconds=dt, draws_per_s=m * n / dt, steps=s2["steps"],
-                              padded_steps=s2["padded_steps"], kernel_ms=s2["kernel_ms"],
+                              padded_steps=s2["padded_steps"],
                               bit_exact_vs_fsm=bool(checksum(out) == ref), speedup_fsm=dt / t_fsm)
     res["sync"] = sync
     del out
