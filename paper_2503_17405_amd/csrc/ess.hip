@@ -15,6 +15,8 @@
 //   * ess_sync_kernel / ess_pad_kernel: the synchronized baseline -- one
 //     draw of every chain per launch; the padding kernel then runs the loop
 //     bodies a batched while loop executes for chains that already exited.
+//   * *_full_kernel: the same kernels for D == 64 x elements per lane, where
+//     the element range masks drop out (same operations on the same values).
 //
 // Both runtimes call the same __device__ functions in the same order for a
 // chain, so their draws agree bit for bit.
