@@ -293,6 +293,10 @@ __device__ __forceinline__ void nu_gemm_block_deep(const NuK<float>& a, int col0
         draw(0, z0);
         put(0, z0);
     }
+    // the first tile's L rows of the next chunk are loaded one chunk ahead
+    const int t0row = tiles[0] >= 0 ? tiles[0] : 0;  // a valid row tile for the address
+    float lrN[16];
+    load_l(lrN, t0row, 0);
     __syncthreads();
     int buf = 0;
     for (int kc = 0; kc < a.Dp; kc += 32) {
@@ -308,8 +312,10 @@ __device__ __forceinline__ void nu_gemm_block_deep(const NuK<float>& a, int col0
             for (int c = 0; c < CT; ++c) av[kk][c] = Zs[buf][16 * h + kk][c * 32 + l32];
         float zn[ZC][4];
         float lrA[16], lrB[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) lrA[i] = lrN[i];
+        load_l(lrN, t0row, more ? kc + 32 : kc);
         if (na > 0) {
-            load_l(lrA, tiles[0], kc);
             load_l(lrB, 1 < na ? tiles[1] : tiles[0], kc);  // tiles[0] exists: no branch
             draw(kc + 32, zn);
 #pragma unroll
