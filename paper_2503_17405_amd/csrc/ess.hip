@@ -276,6 +276,7 @@ static hipError_t prior_draw_t(const JobDev& j, hipStream_t s)
     a.tadd = 0;
     a.t = j.t;
     a.L = (const T*)j.L;
+    a.Lp = (const uint16_t*)j.Lp;
     a.out = (T*)j.x;
     return launch_nu<T>(j, a, j.m, s);
 }

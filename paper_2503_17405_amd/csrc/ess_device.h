@@ -24,6 +24,7 @@ struct NuK {
     const uint32_t* t;  // chain draw counters (or a snapshot of them)
     const T* L;         // Dp x Dp lower factor, zero padded
     T* out;             // column (chain, w) -> out[(chain * W + w) * Dp + row]
+    const uint16_t* Lp; // FP32 with Dp > 768: L = hi + mid + lo, three bf16 planes [3][Dp][Dp]
 };
 
 template <typename T>
@@ -181,75 +182,89 @@ __device__ __forceinline__ void nu_gemm_block_flat(const NuK<float>& a, int col0
 }
 
 // 4 row tiles per wave (Dp <= 1024), the same products in the same order as
-// nu_gemm_block_flat with more registers: one block of 8 waves computes NC = 32 CT
-// columns (col0 ..) over all Dp rows.
-// Wave w owns RT row tiles of 32 rows in "snake" order (w, 15-w, 16+w, 31-w,
-// ...) so the triangular work is balanced across waves; it visits them from
-// the last row tile down, so the tiles that reach K chunk k are a prefix.
-// The K dimension is walked in chunks of 32 with one barrier per chunk.  Per
-// chunk a wave reads its Z operands from LDS once (shared by its row tiles),
-// loads the L rows of its next tile (float4 along k) while the MFMAs of the
-// current one run (v_mfma_f32_32x32x2f32, FP32 accumulation), and draws its
-// normals of chunk k+1 (one Philox block per thread and 64 columns) in
-// between the MFMAs of its first tile; they go to the other LDS buffer after
-// the chunk.  The MFMA computes nu^T = z^T L^T so each output register row is
-// 32 consecutive nu entries of one column (128-byte coalesced stores).  The
-// products and their order per output element do not depend on any of this
-// scheduling.  A block whose columns are all past their chain's last draw
-// exits at once.
-template <int RT, int CT = 2>
-__device__ __forceinline__ void nu_gemm_block_deep(const NuK<float>& a, int col0)
+// x = hi + mid + lo exactly, each piece a bf16 bit pattern: hi keeps the top 16
+// bits of x, the remainder x - hi (at most 16 significant bits) is exact in
+// FP32, mid keeps its top 16 bits and the rest (at most 8 significant bits)
+// is lo.  The host splits L the same way.
+__device__ __forceinline__ void split_bf16x3(float x, uint32_t& hi, uint32_t& mid, uint32_t& lo)
 {
-    static_assert(CT == 2 || CT == 4, "64 or 128 columns per block");
-    constexpr int NC = 32 * CT, ZC = CT / 2;
-    __shared__ float Zs[2][32][NC];
+    const uint32_t uh = __float_as_uint(x) & 0xFFFF0000u;
+    const float r1 = x - __uint_as_float(uh);
+    const uint32_t um = __float_as_uint(r1) & 0xFFFF0000u;
+    const float r2 = r1 - __uint_as_float(um);
+    hi = uh >> 16;
+    mid = um >> 16;
+    lo = __float_as_uint(r2) >> 16;
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// The 4-tile shape (Dp > 768) on the bf16 matrix cores.  z and L are split
+// exactly into three bf16 pieces each, and every 16-k block of a 32 x 32 tile
+// takes the six piece products down to relative order 2^-16 (lo*hi, mid*mid,
+// hi*lo, mid*hi, hi*mid, hi*hi; v_mfma_f32_32x32x16_bf16, FP32 accumulation):
+// the dropped ones are below 2^-23 of the product, so the result has FP32
+// accuracy at 6 bf16 products per FP32 product (the bf16 cores run 16 times
+// the FP32 MFMA rate).
+// One block of 8 waves computes 64 columns (col0 ..) over all Dp rows; wave w
+// owns 4 row tiles in snake order (last row tile first, so the tiles that
+// reach K chunk k are a prefix).  Per chunk of 32 k: the z pieces come from
+// LDS ([piece][column][k], rows padded to 40 halfwords so the 16-byte reads
+// do not conflict), the thread draws its 4 normals of the next chunk and
+// stores their pieces in the other LDS buffer, and the (tile, k-block) pairs
+// run in order with the next pair's L pieces (16-byte loads from the planes)
+// in flight -- the last pair loads the next chunk's first one.  The products
+// and their order per output element do not depend on this scheduling.  A
+// block whose columns are all past their chain's last draw exits at once.
+// The directions are written with nontemporal stores (they are read once, by
+// the next window's kernel), which keeps L's planes in L2.
+template <int RT, int CT = 2>
+__device__ __forceinline__ void nu_gemm_block_bf16(const NuK<float>& a, int col0)
+{
+    static_assert(CT == 2, "64 columns per block");
+    constexpr int NC = 32 * CT, KR = 40;
+    __shared__ uint16_t Zs[2][3][NC][KR];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, l32 = lane & 31;
     const int ncols = a.m * a.W;
 
     const int zc = tid & 63, zb = tid >> 6;
-    bool zvalid[ZC];
-    int zchain[ZC];
-    uint32_t zdraw[ZC];
-    int any = 0;
-#pragma unroll
-    for (int cc = 0; cc < ZC; ++cc) {
-        const int gcol = col0 + zc + 64 * cc;
-        zvalid[cc] = gcol < ncols;
-        zchain[cc] = 0;
-        zdraw[cc] = 0;
-        if (zvalid[cc]) {
-            zchain[cc] = gcol / a.W;
-            const int zw = gcol - zchain[cc] * a.W;
-            zdraw[cc] = a.draw_fixed >= 0 ? (uint32_t)a.draw_fixed : a.t[zchain[cc]] + a.tadd + (uint32_t)zw;
-            zvalid[cc] = a.draw_fixed >= 0 || zdraw[cc] < (uint32_t)a.n;
+    bool zvalid = false;
+    int zchain = 0;
+    uint32_t zdraw = 0;
+    {
+        const int gcol = col0 + zc;
+        zvalid = gcol < ncols;
+        if (zvalid) {
+            zchain = gcol / a.W;
+            const int zw = gcol - zchain * a.W;
+            zdraw = a.draw_fixed >= 0 ? (uint32_t)a.draw_fixed : a.t[zchain] + a.tadd + (uint32_t)zw;
+            zvalid = a.draw_fixed >= 0 || zdraw < (uint32_t)a.n;
         }
-        any |= zvalid[cc] ? 1 : 0;
     }
-    if (!__syncthreads_or(any)) return;
+    if (!__syncthreads_or(zvalid ? 1 : 0)) return;
 
-    // this thread's 4 normals (rows kc + 4 zb .. + 3) per column group; +0 where
-    // the row or the column does not exist.  No branches (the mask is applied
-    // with an opaque AND), so the compiler can place them between MFMAs.
-    auto draw = [&](int kc, float (&z)[ZC][4]) {
+    // this thread's 4 normals (rows kc + 4 zb .. + 3 of column zc; 0 past D or
+    // for a missing column), split, as 4 consecutive k in each piece plane
+    auto draw_put = [&](int kc, int buf) {
         const int kb = kc + 4 * zb;
+        float z[4];
+        normals4<float>(a.seed, (uint32_t)zchain, zdraw, a.role, 0, (uint32_t)(kb >> 2), z);
 #pragma unroll
-        for (int cc = 0; cc < ZC; ++cc) {
-            normals4<float>(a.seed, (uint32_t)zchain[cc], zdraw[cc], a.role, 0, (uint32_t)(kb >> 2), z[cc]);
+        for (int i = 0; i < 4; i += 2) {
+            uint32_t pc[2][3];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t keep = (zvalid[cc] && kb + i < a.D) ? 0xFFFFFFFFu : 0u;
+            for (int j = 0; j < 2; ++j) {
+                const uint32_t keep = (zvalid && kb + i + j < a.D) ? 0xFFFFFFFFu : 0u;
                 uint32_t bits;
-                asm("v_and_b32 %0, %1, %2" : "=v"(bits) : "v"(__float_as_uint(z[cc][i])), "v"(keep));
-                z[cc][i] = __uint_as_float(bits);
+                asm("v_and_b32 %0, %1, %2" : "=v"(bits) : "v"(__float_as_uint(z[i + j])), "v"(keep));
+                split_bf16x3(__uint_as_float(bits), pc[j][0], pc[j][1], pc[j][2]);
             }
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                *reinterpret_cast<uint32_t*>(&Zs[buf][q][zc][4 * zb + i]) = pc[0][q] | (pc[1][q] << 16);
         }
-    };
-    auto put = [&](int buf, const float (&z)[ZC][4]) {
-#pragma unroll
-        for (int cc = 0; cc < ZC; ++cc)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) Zs[buf][4 * zb + i][zc + 64 * cc] = z[cc][i];
     };
 
     // the wave's row tiles, last first; missing ones (-1) at the end
@@ -275,28 +290,19 @@ __device__ __forceinline__ void nu_gemm_block_deep(const NuK<float>& a, int col0
         for (int c = 0; c < CT; ++c)
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[r][c][q] = 0.0f;
-    // L[32 ti + l32][kc + 16 h .. + 15]
-    auto load_l = [&](float (&lr)[16], int ti, int kc) {
-        const float4* Lr = reinterpret_cast<const float4*>(a.L + (size_t)(32 * ti + l32) * a.Dp + kc + 16 * h);
+
+    // pieces of L[32 ti + l32][k0 + 8 h .. + 7]
+    const size_t plane = (size_t)a.Dp * a.Dp;
+    auto load_l = [&](u32x4 (&lr)[3], int ti, int k0) {
+        const uint16_t* base = a.Lp + (size_t)(32 * ti + l32) * a.Dp + k0 + 8 * h;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const float4 q4 = Lr[v];
-            lr[4 * v + 0] = q4.x;
-            lr[4 * v + 1] = q4.y;
-            lr[4 * v + 2] = q4.z;
-            lr[4 * v + 3] = q4.w;
-        }
+        for (int p = 0; p < 3; ++p) lr[p] = *reinterpret_cast<const u32x4*>(base + p * plane);
     };
 
-    {
-        float z0[ZC][4];
-        draw(0, z0);
-        put(0, z0);
-    }
-    // the first tile's L rows of the next chunk are loaded one chunk ahead
+    draw_put(0, 0);
     const int t0row = tiles[0] >= 0 ? tiles[0] : 0;  // a valid row tile for the address
-    float lrN[16];
-    load_l(lrN, t0row, 0);
+    u32x4 lb[2][3];
+    load_l(lb[0], t0row, 0);
     __syncthreads();
     int buf = 0;
     for (int kc = 0; kc < a.Dp; kc += 32) {
@@ -305,46 +311,45 @@ __device__ __forceinline__ void nu_gemm_block_deep(const NuK<float>& a, int col0
 #pragma unroll
         for (int r = 0; r < RT; ++r) na += (tiles[r] >= 0 && 32 * tiles[r] + 31 >= kc) ? 1 : 0;
         na = uni(na);
-        float av[16][CT];
+        if (more) draw_put(kc + 32, buf ^ 1);
+        // za[kb][c][p]: piece p of z rows kc + 16 kb + 8 h .. + 7, column 32 c + l32
+        u32x4 za[2][CT][3];
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk)
+        for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-            for (int c = 0; c < CT; ++c) av[kk][c] = Zs[buf][16 * h + kk][c * 32 + l32];
-        float zn[ZC][4];
-        float lrA[16], lrB[16];
+            for (int c = 0; c < CT; ++c)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) lrA[i] = lrN[i];
-        load_l(lrN, t0row, more ? kc + 32 : kc);
-        if (na > 0) {
-            load_l(lrB, 1 < na ? tiles[1] : tiles[0], kc);  // tiles[0] exists: no branch
-            draw(kc + 32, zn);
+                for (int p = 0; p < 3; ++p)
+                    za[kb][c][p] = *reinterpret_cast<const u32x4*>(&Zs[buf][p][32 * c + l32][16 * kb + 8 * h]);
+        // pair q = (tile q / 2, k-block q % 2) uses lb[q % 2] and loads pair q + 1
 #pragma unroll
-            for (int kk = 0; kk < 16; ++kk)
-#pragma unroll
-                for (int c = 0; c < CT; ++c)
-                    acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk][c], lrA[kk], acc[0][c], 0, 0, 0);
-            // interleave: one MFMA, then up to 6 VALU instructions (the normals)
-#pragma unroll
-            for (int i = 0; i < 16 * CT; ++i) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
-            }
-        } else {
-            draw(kc + 32, zn);
-        }
-#pragma unroll
-        for (int r = 1; r < RT; ++r) {
+        for (int q = 0; q < 2 * RT; ++q) {
+            const int r = q >> 1, kb = q & 1;
             if (r >= na) break;
-            float(&cur)[16] = (r & 1) ? lrB : lrA;
-            float(&nxt)[16] = (r & 1) ? lrA : lrB;
-            if (r + 1 < na) load_l(nxt, tiles[r + 1], kc);
+            u32x4(&cur)[3] = lb[q & 1];
+            u32x4(&nxt)[3] = lb[(q + 1) & 1];
+            if (q + 1 < 2 * na)
+                load_l(nxt, tiles[(q + 1) >> 1], kc + 16 * ((q + 1) & 1));
+            else
+                load_l(nxt, t0row, more ? kc + 32 : kc);
 #pragma unroll
-            for (int kk = 0; kk < 16; ++kk)
-#pragma unroll
-                for (int c = 0; c < CT; ++c)
-                    acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk][c], cur[kk], acc[r][c], 0, 0, 0);
+            for (int c = 0; c < CT; ++c) {
+                const bf16x8 zh = __builtin_bit_cast(bf16x8, za[kb][c][0]);
+                const bf16x8 zm = __builtin_bit_cast(bf16x8, za[kb][c][1]);
+                const bf16x8 zl = __builtin_bit_cast(bf16x8, za[kb][c][2]);
+                const bf16x8 Lh = __builtin_bit_cast(bf16x8, cur[0]);
+                const bf16x8 Lm = __builtin_bit_cast(bf16x8, cur[1]);
+                const bf16x8 Ll = __builtin_bit_cast(bf16x8, cur[2]);
+                floatx16 t = acc[r][c];
+                t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(zl, Lh, t, 0, 0, 0);
+                t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(zm, Lm, t, 0, 0, 0);
+                t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(zh, Ll, t, 0, 0, 0);
+                t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(zm, Lh, t, 0, 0, 0);
+                t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(zh, Lm, t, 0, 0, 0);
+                t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(zh, Lh, t, 0, 0, 0);
+                acc[r][c] = t;
+            }
         }
-        if (more) put(buf ^ 1, zn);
         __syncthreads();
         buf ^= 1;
     }
@@ -358,20 +363,20 @@ __device__ __forceinline__ void nu_gemm_block_deep(const NuK<float>& a, int col0
             float* o = a.out + (size_t)g * a.Dp + l32;
 #pragma unroll
             for (int r = 0; r < RT; ++r)
-                if (tiles[r] >= 0) o[32 * tiles[r]] = acc[r][c][q];
+                if (tiles[r] >= 0) __builtin_nontemporal_store(acc[r][c][q], o + 32 * tiles[r]);
         }
     }
 }
 
-// Ellipse-direction product for the columns col0 .. col0 + 32 CT - 1 of a window.
-// Both variants give the same bits; the deep one hides the normals and the L
-// loads behind the MFMAs and pays for it in registers, which only the 4-tile
-// shape can spare without losing waves.
+// Ellipse-direction product for the columns col0 .. col0 + 32 CT - 1 of a window:
+// FP32 MFMA up to 3 row tiles per wave (Dp <= 768), the bf16 matrix cores with
+// exact three-piece splits above.  A job's padded dimension fixes the variant,
+// so every kernel that computes its directions gives the same bits.
 template <int RT, int CT = 2>
 __device__ __forceinline__ void nu_gemm_block(const NuK<float>& a, int col0)
 {
     if constexpr (RT >= 4)
-        nu_gemm_block_deep<RT, CT>(a, col0);
+        nu_gemm_block_bf16<RT, CT>(a, col0);
     else
         nu_gemm_block_flat<RT, CT>(a, col0);
 }
@@ -631,11 +636,10 @@ inline NuK<T> ess_window_view(const JobDev& j, int buf = 0, const uint32_t* t = 
     a.tadd = tadd;
     a.t = t ? t : j.t;
     a.L = (const T*)j.L;
+    a.Lp = (const uint16_t*)j.Lp;
     a.out = (T*)j.nu + (size_t)buf * j.m * j.Wcap * j.Dp;
     return a;
 }
 
-// Row tiles of 32 per GEMM wave (8 waves) for the job's padded dimension.
-inline int ess_gemm_rt(int Dp) { return (Dp / 32 + 7) / 8; }
 
 }  // namespace fsmmc

@@ -230,12 +230,40 @@ fsmmc_status fsmmc::validate_specs(const fsmmc_target_spec* t, const fsmmc_sampl
 // lower-triangular device buffer (entries above the diagonal dropped).
 extern "C" {
 
-static fsmmc_status stage_lower(fsmmc_job* job, const void* src, int D, int Dp, size_t es, void* dst)
+// The lower triangle of L, zero padded to Dp x Dp.  With `planes`, also its
+// exact three-piece bf16 split (hi, mid, lo; the same truncations as the
+// device's split of z) for the bf16 ellipse GEMM, as planes [3][Dp][Dp].
+static fsmmc_status stage_lower(fsmmc_job* job, const void* src, int D, int Dp, size_t es, void* dst,
+                                void* planes)
 {
     std::vector<unsigned char> h((size_t)D * D * es), p((size_t)Dp * Dp * es, 0);
     HIP_TRY(hipMemcpy(h.data(), src, h.size(), hipMemcpyDeviceToHost));
     for (int r = 0; r < D; ++r) std::memcpy(&p[(size_t)r * Dp * es], &h[(size_t)r * D * es], (size_t)(r + 1) * es);
     HIP_TRY(hipMemcpyAsync(dst, p.data(), p.size(), hipMemcpyHostToDevice, job->stream));
+    std::vector<uint16_t> pl;
+    if (planes) {
+        const size_t n = (size_t)Dp * Dp;
+        pl.assign(3 * n, 0);
+        for (size_t i = 0; i < n; ++i) {
+            float x;
+            std::memcpy(&x, &p[i * 4], 4);
+            uint32_t u, v, w;
+            std::memcpy(&u, &x, 4);
+            const uint32_t uh = u & 0xFFFF0000u;
+            float fh, fm;
+            std::memcpy(&fh, &uh, 4);
+            const float r1 = x - fh;
+            std::memcpy(&v, &r1, 4);
+            const uint32_t um = v & 0xFFFF0000u;
+            std::memcpy(&fm, &um, 4);
+            const float r2 = r1 - fm;
+            std::memcpy(&w, &r2, 4);
+            pl[i] = (uint16_t)(uh >> 16);
+            pl[n + i] = (uint16_t)(um >> 16);
+            pl[2 * n + i] = (uint16_t)(w >> 16);
+        }
+        HIP_TRY(hipMemcpyAsync(planes, pl.data(), pl.size() * 2, hipMemcpyHostToDevice, job->stream));
+    }
     HIP_TRY(hipStreamSynchronize(job->stream));
     return FSMMC_OK;
 }
@@ -300,6 +328,7 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
         ALLOC(d.sink, m * es);
         ALLOC(d.maxN, (size_t)d.n * 4);
         ALLOC(d.L, Dp * Dp * es);
+        if (d.dtype == FSMMC_F32 && ess_gemm_rt(d.Dp) >= 4) ALLOC(d.Lp, 3 * Dp * Dp * sizeof(uint16_t));
         ALLOC(d.y, Dp * es);
         // ellipse window: about 1 GiB of directions, 4..256 draws, at most n
         int W = tune && tune->window > 0 ? tune->window : 0;
@@ -316,7 +345,7 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
         HIP_TRY_JOB(hipStreamCreateWithFlags(&job->side, hipStreamNonBlocking));
         HIP_TRY_JOB(hipEventCreateWithFlags(&job->ev_snap, hipEventDisableTiming));
         HIP_TRY_JOB(hipEventCreateWithFlags(&job->ev_gemm, hipEventDisableTiming));
-        fsmmc_status s2 = stage_lower(job, target->chol_L, d.D, d.Dp, es, d.L);
+        fsmmc_status s2 = stage_lower(job, target->chol_L, d.D, d.Dp, es, d.L, d.Lp);
         if (s2 != FSMMC_OK) {
             job_release(job);
             return s2;

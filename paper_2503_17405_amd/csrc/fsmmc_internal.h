@@ -30,6 +30,7 @@ struct JobDev {
 
     // target data (owned copies)
     void* L = nullptr;  // Dp x Dp, zero padded (GP)
+    void* Lp = nullptr; // FP32 GP with Dp > 768: L's bf16 pieces hi, mid, lo, planes [3][Dp][Dp]
     void* y = nullptr;  // Dp (GP) or Np (LOGREG) labels / observations
     void* X = nullptr;  // LOGREG: Np x Dp, zero padded
     void* prec = nullptr;
@@ -109,5 +110,9 @@ hipError_t dr_init_state(const JobDev& j, const void* x0, hipStream_t s);
 hipError_t dr_fsm_round(const JobDev& j, hipStream_t s);
 hipError_t dr_sync_draw(const JobDev& j, uint32_t draw, hipStream_t s);
 hipError_t dr_pad_draw(const JobDev& j, uint32_t draw, hipStream_t s);
+
+// Row tiles of 32 per ellipse-GEMM wave (8 waves) for a padded dimension;
+// 4 selects the bf16 variant, which needs L's bf16 planes.
+inline int ess_gemm_rt(int Dp) { return (Dp / 32 + 7) / 8; }
 
 }  // namespace fsmmc
