@@ -24,7 +24,7 @@ struct NuK {
     const uint32_t* t;  // chain draw counters (or a snapshot of them)
     const T* L;         // Dp x Dp lower factor, zero padded
     T* out;             // column (chain, w) -> out[(chain * W + w) * Dp + row]
-    const uint16_t* Lp; // FP32 with Dp > 768: L = hi + mid + lo, three bf16 planes [3][Dp][Dp]
+    const uint16_t* Lp; // FP32 with Dp > 768: L = hi + mid + lo in bf16, packed by (row tile, chunk)
 };
 
 template <typename T>
@@ -213,8 +213,11 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // LDS ([piece][column][k], rows padded to 40 halfwords so the 16-byte reads
 // do not conflict), the thread draws its 4 normals of the next chunk and
 // stores their pieces in the other LDS buffer, and the (tile, k-block) pairs
-// run in order with the next pair's L pieces (16-byte loads from the planes)
-// in flight -- the last pair loads the next chunk's first one.  The products
+// run in order with the next pair's L pieces in flight -- the last pair loads
+// the next chunk's first one.  L's pieces are packed so that one pair's are
+// contiguous: for row tile ti, chunk c <= ti, k-block kb and piece p, the
+// 32 x 16 block L[32 ti + r][32 c + 16 kb + kk] is 512 halfwords [r][kk] at
+// ((ti (ti + 1) / 2 + c) 2 + kb) 3 + p blocks (each load fills whole lines).  The products
 // and their order per output element do not depend on this scheduling.  A
 // block whose columns are all past their chain's last draw exits at once.
 // The directions are written with nontemporal stores (they are read once, by
@@ -283,6 +286,8 @@ __device__ __forceinline__ void nu_gemm_block_bf16(const NuK<float>& a, int col0
             ++nt;
         }
     }
+#pragma unroll
+    for (int r = 0; r < RT; ++r) tiles[r] = uni(tiles[r]);
     floatx16 acc[RT][CT];
 #pragma unroll
     for (int r = 0; r < RT; ++r)
@@ -291,12 +296,13 @@ __device__ __forceinline__ void nu_gemm_block_bf16(const NuK<float>& a, int col0
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[r][c][q] = 0.0f;
 
-    // pieces of L[32 ti + l32][k0 + 8 h .. + 7]
-    const size_t plane = (size_t)a.Dp * a.Dp;
+    // pieces of L[32 ti + l32][k0 + 8 h .. + 7] (k0 a multiple of 16; a chunk
+    // past the diagonal, only ever prefetched and unused, reads the diagonal's)
     auto load_l = [&](u32x4 (&lr)[3], int ti, int k0) {
-        const uint16_t* base = a.Lp + (size_t)(32 * ti + l32) * a.Dp + k0 + 8 * h;
+        const int c = min(k0 >> 5, ti), kb = (k0 >> 4) & 1;
+        const uint16_t* base = a.Lp + (size_t)(((ti * (ti + 1) / 2 + c) * 2 + kb) * 3) * 512 + 16 * l32 + 8 * h;
 #pragma unroll
-        for (int p = 0; p < 3; ++p) lr[p] = *reinterpret_cast<const u32x4*>(base + p * plane);
+        for (int p = 0; p < 3; ++p) lr[p] = *reinterpret_cast<const u32x4*>(base + 512 * p);
     };
 
     draw_put(0, 0);

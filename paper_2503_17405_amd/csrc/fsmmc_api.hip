@@ -232,7 +232,8 @@ extern "C" {
 
 // The lower triangle of L, zero padded to Dp x Dp.  With `planes`, also its
 // exact three-piece bf16 split (hi, mid, lo; the same truncations as the
-// device's split of z) for the bf16 ellipse GEMM, as planes [3][Dp][Dp].
+// device's split of z) for the bf16 ellipse GEMM, packed per (row tile ti,
+// chunk c <= ti, k-block kb, piece p) as 32 x 16 blocks [row][k].
 static fsmmc_status stage_lower(fsmmc_job* job, const void* src, int D, int Dp, size_t es, void* dst,
                                 void* planes)
 {
@@ -242,26 +243,32 @@ static fsmmc_status stage_lower(fsmmc_job* job, const void* src, int D, int Dp, 
     HIP_TRY(hipMemcpyAsync(dst, p.data(), p.size(), hipMemcpyHostToDevice, job->stream));
     std::vector<uint16_t> pl;
     if (planes) {
-        const size_t n = (size_t)Dp * Dp;
-        pl.assign(3 * n, 0);
-        for (size_t i = 0; i < n; ++i) {
-            float x;
-            std::memcpy(&x, &p[i * 4], 4);
-            uint32_t u, v, w;
-            std::memcpy(&u, &x, 4);
-            const uint32_t uh = u & 0xFFFF0000u;
-            float fh, fm;
-            std::memcpy(&fh, &uh, 4);
-            const float r1 = x - fh;
-            std::memcpy(&v, &r1, 4);
-            const uint32_t um = v & 0xFFFF0000u;
-            std::memcpy(&fm, &um, 4);
-            const float r2 = r1 - fm;
-            std::memcpy(&w, &r2, 4);
-            pl[i] = (uint16_t)(uh >> 16);
-            pl[n + i] = (uint16_t)(um >> 16);
-            pl[2 * n + i] = (uint16_t)(w >> 16);
-        }
+        pl.assign(ess_lower_pieces_halfwords(Dp), 0);
+        const int nt = Dp / 32;
+        size_t blk = 0;  // ((ti (ti + 1) / 2 + c) 2 + kb) 3 + piece
+        for (int ti = 0; ti < nt; ++ti)
+            for (int c = 0; c <= ti; ++c)
+                for (int kb = 0; kb < 2; ++kb, blk += 3)
+                    for (int r = 0; r < 32; ++r)
+                        for (int kk = 0; kk < 16; ++kk) {
+                            float x;
+                            std::memcpy(&x, &p[((size_t)(32 * ti + r) * Dp + 32 * c + 16 * kb + kk) * 4], 4);
+                            uint32_t u, v, w;
+                            std::memcpy(&u, &x, 4);
+                            const uint32_t uh = u & 0xFFFF0000u;
+                            float fh, fm;
+                            std::memcpy(&fh, &uh, 4);
+                            const float r1 = x - fh;
+                            std::memcpy(&v, &r1, 4);
+                            const uint32_t um = v & 0xFFFF0000u;
+                            std::memcpy(&fm, &um, 4);
+                            const float r2 = r1 - fm;
+                            std::memcpy(&w, &r2, 4);
+                            const size_t at = 16 * r + kk;
+                            pl[blk * 512 + at] = (uint16_t)(uh >> 16);
+                            pl[(blk + 1) * 512 + at] = (uint16_t)(um >> 16);
+                            pl[(blk + 2) * 512 + at] = (uint16_t)(w >> 16);
+                        }
         HIP_TRY(hipMemcpyAsync(planes, pl.data(), pl.size() * 2, hipMemcpyHostToDevice, job->stream));
     }
     HIP_TRY(hipStreamSynchronize(job->stream));
@@ -328,7 +335,7 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
         ALLOC(d.sink, m * es);
         ALLOC(d.maxN, (size_t)d.n * 4);
         ALLOC(d.L, Dp * Dp * es);
-        if (d.dtype == FSMMC_F32 && ess_gemm_rt(d.Dp) >= 4) ALLOC(d.Lp, 3 * Dp * Dp * sizeof(uint16_t));
+        if (d.dtype == FSMMC_F32 && ess_gemm_rt(d.Dp) >= 4) ALLOC(d.Lp, ess_lower_pieces_halfwords(d.Dp) * sizeof(uint16_t));
         ALLOC(d.y, Dp * es);
         // ellipse window: about 1 GiB of directions, 4..256 draws, at most n
         int W = tune && tune->window > 0 ? tune->window : 0;
