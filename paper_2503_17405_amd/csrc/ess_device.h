@@ -58,7 +58,8 @@ struct EssK {
 // computes nu^T = z^T L^T so each output register row is 32 consecutive nu
 // entries of one column (128-byte coalesced stores).  The products and their
 // order per output element do not depend on the pipelining.  A block whose
-// columns are all past their chain's last draw exits at once.
+// columns are all past their chain's last draw exits at once.  The directions
+// go out with nontemporal stores (the next window's kernel reads them once).
 template <int RT, int CT = 2>
 __device__ __forceinline__ void nu_gemm_block_flat(const NuK<float>& a, int col0)
 {
@@ -176,12 +177,11 @@ __device__ __forceinline__ void nu_gemm_block_flat(const NuK<float>& a, int col0
             float* o = a.out + (size_t)g * a.Dp + l32;
 #pragma unroll
             for (int r = 0; r < RT; ++r)
-                if (tiles[r] >= 0) o[32 * tiles[r]] = acc[r][c][q];
+                if (tiles[r] >= 0) __builtin_nontemporal_store(acc[r][c][q], o + 32 * tiles[r]);
         }
     }
 }
 
-// 4 row tiles per wave (Dp <= 1024), the same products in the same order as
 // x = hi + mid + lo exactly, each piece a bf16 bit pattern: hi keeps the top 16
 // bits of x, the remainder x - hi (at most 16 significant bits) is exact in
 // FP32, mid keeps its top 16 bits and the rest (at most 8 significant bits)
