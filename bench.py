@@ -160,15 +160,20 @@ def bench_ess(F, ctx, args):
     # the same job with a finite step budget runs its windows one after another:
     # the GEMM launches then have the chip to themselves
     log("ESS FSM, windows not overlapped")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     job = make()
     while not job.step_fsm(1 << 40):
         pass
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
     si = job.stats()
     job.free()
     gi_ms, gi_n = si["kernel_ms"][0], si["kernel_launches"][0]
     res["gemm_isolated"] = dict(ms=gi_ms, launches=gi_n, avg_us=1e3 * gi_ms / max(gi_n, 1),
                                 tflops=flops / (gi_ms * 1e-3) / 1e12,
-                                bit_exact_vs_fsm=bool(checksum(out) == ref))
+                                bit_exact_vs_fsm=bool(checksum(out) == ref),
+                                job_seconds=t_seq)
     sync = {}
     if not args.no_sync:
         for name, mode in (("vmap", F.SYNC_VMAP), ("compact", F.SYNC_COMPACT)):
