@@ -5,7 +5,9 @@ Headline workload (value): elliptical slice sampling of a D = 1024 latent
 Gaussian process (inputs uniform on [0, 1], squared-exponential prior,
 lengthscale 0.05, jitter 1e-5) with a Bernoulli-logistic likelihood whose
 labels come from a seeded prior draw; 8192 chains x 2000 draws, FP32,
-ellipse directions L z on FP32 MFMA.  One step = one complete sampling job
+ellipse directions L z to FP32 accuracy on the bf16 matrix cores (exact
+three-piece bf16 splits of z and L, six piece products per FP32 product,
+FP32 accumulation).  One step = one complete sampling job
 (init_chains + every chain to 2000 draws) through the C ABI; inputs (L,
 labels) are resident in HBM before the timed region.
 
