@@ -531,6 +531,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
+        "arithmetic": "FP32 throughout; the direction GEMM (Dp > 512) multiplies exact three-piece bf16 "
+                      "splits of its FP32 operands on the bf16 matrix cores (six piece products per FP32 "
+                      "product, FP32 accumulation) and matches the FP32 product to ~1e-6",
         "data": "synthetic",
         "config": {"workload": "ESS GP-logistic D=1024 (SE lengthscale 0.05, jitter 1e-5), "
                                "%d chains x %d draws, FP32; one step = one whole sampling job"
