@@ -242,7 +242,7 @@ typedef struct {
                                 direction buffer each job was created with           */
     int32_t dr_chunk;        /* DRMH draws per chain per round (0 = 16)              */
     int32_t gemm_cols;       /* ellipse GEMM columns per block, 64 or 128 (0 = 64;
-                                128 applies to jobs with dim <= 512)                 */
+                                128 applies to FP32 jobs with dim <= 256)            */
     int32_t rounds_per_sync; /* graph replays between progress reads (0 = 4)         */
     int32_t nuts_steps;      /* NUTS runtime steps per round (0 = 16)                */
     int32_t reserved[2];

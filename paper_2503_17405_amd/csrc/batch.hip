@@ -248,7 +248,6 @@ hipError_t launch_tiles(int slot, int ntiles, const BJob* jobs, const BTile* til
     case 0: hipLaunchKernelGGL((batch_nu_kernel<1, 2>), g, b, 0, s, jobs, tiles); break;
     case 1: hipLaunchKernelGGL((batch_nu_kernel<1, 4>), g, b, 0, s, jobs, tiles); break;
     case 2: hipLaunchKernelGGL((batch_nu_kernel<2, 2>), g, b, 0, s, jobs, tiles); break;
-    case 3: hipLaunchKernelGGL((batch_nu_kernel<2, 4>), g, b, 0, s, jobs, tiles); break;
     case 4: hipLaunchKernelGGL((batch_nu_kernel<3, 2>), g, b, 0, s, jobs, tiles); break;
     case 6: hipLaunchKernelGGL((batch_nu_kernel<4, 2>), g, b, 0, s, jobs, tiles); break;
     default: return hipErrorInvalidValue;
@@ -343,7 +342,7 @@ fsmmc_status rebuild(fsmmc_batch* b)
             const double cost = (double)d.W * (d.EPL + 2);
             for (int c = 0; c < d.m; ++c) items.push_back({cost, BItem{i, c}});
             const int rt = ess_gemm_rt(d.Dp);
-            const int ct = (b->cols == 128 && rt <= 2) ? 4 : 2;
+            const int ct = (b->cols == 128 && rt <= 1) ? 4 : 2;  // the bf16 shapes (rt >= 2) take 64
             const int ncols = d.m * d.W;
             for (int c0 = 0; c0 < ncols; c0 += 32 * ct) tiles[tile_slot(rt, ct)].push_back(BTile{i, c0});
         } else if (d.kind == FSMMC_DRMH) {

@@ -24,7 +24,7 @@ struct NuK {
     const uint32_t* t;  // chain draw counters (or a snapshot of them)
     const T* L;         // Dp x Dp lower factor, zero padded
     T* out;             // column (chain, w) -> out[(chain * W + w) * Dp + row]
-    const uint16_t* Lp; // FP32 with Dp > 512: L = hi + mid + lo in bf16, packed by (row tile, chunk)
+    const uint16_t* Lp; // FP32 with Dp > 256: L = hi + mid + lo in bf16, packed by (row tile, chunk)
 };
 
 template <typename T>
@@ -46,7 +46,7 @@ struct EssK {
 };
 
 // ------------------------------------------------------------ ellipse GEMM
-// Up to 2 row tiles per wave (Dp <= 512): one block of 8 waves computes NC = 32 CT
+// One row tile per wave (Dp <= 256): one block of 8 waves computes NC = 32 CT
 // columns (col0 ..) over all Dp rows.
 // Wave w owns RT row tiles of 32 rows in "snake" order (w, 15-w, 16+w, 31-w,
 // ...) so the triangular work is balanced across waves.  The K dimension is
@@ -200,7 +200,7 @@ __device__ __forceinline__ void split_bf16x3(float x, uint32_t& hi, uint32_t& mi
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// The 3- and 4-tile shapes (Dp > 512) on the bf16 matrix cores.  z and L are split
+// The 2- to 4-tile shapes (Dp > 256) on the bf16 matrix cores.  z and L are split
 // exactly into three bf16 pieces each, and every 16-k block of a 32 x 32 tile
 // takes the six piece products down to relative order 2^-16 (lo*hi, mid*mid,
 // hi*lo, mid*hi, hi*mid, hi*hi; v_mfma_f32_32x32x16_bf16, FP32 accumulation):
@@ -375,13 +375,13 @@ __device__ __forceinline__ void nu_gemm_block_bf16(const NuK<float>& a, int col0
 }
 
 // Ellipse-direction product for the columns col0 .. col0 + 32 CT - 1 of a window:
-// FP32 MFMA up to 2 row tiles per wave (Dp <= 512), the bf16 matrix cores with
+// FP32 MFMA for one row tile per wave (Dp <= 256), the bf16 matrix cores with
 // exact three-piece splits above.  A job's padded dimension fixes the variant,
 // so every kernel that computes its directions gives the same bits.
 template <int RT, int CT = 2>
 __device__ __forceinline__ void nu_gemm_block(const NuK<float>& a, int col0)
 {
-    if constexpr (RT >= 3)
+    if constexpr (RT >= 2)
         nu_gemm_block_bf16<RT, CT>(a, col0);
     else
         nu_gemm_block_flat<RT, CT>(a, col0);

@@ -335,7 +335,7 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
         ALLOC(d.sink, m * es);
         ALLOC(d.maxN, (size_t)d.n * 4);
         ALLOC(d.L, Dp * Dp * es);
-        if (d.dtype == FSMMC_F32 && ess_gemm_rt(d.Dp) >= 3) ALLOC(d.Lp, ess_lower_pieces_halfwords(d.Dp) * sizeof(uint16_t));
+        if (d.dtype == FSMMC_F32 && ess_gemm_rt(d.Dp) >= 2) ALLOC(d.Lp, ess_lower_pieces_halfwords(d.Dp) * sizeof(uint16_t));
         ALLOC(d.y, Dp * es);
         // ellipse window: about 1 GiB of directions, 4..256 draws, at most n
         int W = tune && tune->window > 0 ? tune->window : 0;

@@ -30,7 +30,7 @@ struct JobDev {
 
     // target data (owned copies)
     void* L = nullptr;  // Dp x Dp, zero padded (GP)
-    void* Lp = nullptr; // FP32 GP with Dp > 512: L's bf16 pieces, packed (ess_lower_pieces_halfwords)
+    void* Lp = nullptr; // FP32 GP with Dp > 256: L's bf16 pieces, packed (ess_lower_pieces_halfwords)
     void* y = nullptr;  // Dp (GP) or Np (LOGREG) labels / observations
     void* X = nullptr;  // LOGREG: Np x Dp, zero padded
     void* prec = nullptr;
@@ -112,7 +112,7 @@ hipError_t dr_sync_draw(const JobDev& j, uint32_t draw, hipStream_t s);
 hipError_t dr_pad_draw(const JobDev& j, uint32_t draw, hipStream_t s);
 
 // Row tiles of 32 per ellipse-GEMM wave (8 waves) for a padded dimension;
-// 3 and 4 select the bf16 variant, which needs L's packed bf16 pieces.
+// 2 to 4 select the bf16 variant, which needs L's packed bf16 pieces.
 inline int ess_gemm_rt(int Dp) { return (Dp / 32 + 7) / 8; }
 // Size of L's packed bf16 pieces: per row tile ti and chunk c <= ti, two
 // k-blocks of three 32 x 16 pieces.

@@ -129,9 +129,9 @@ def test_ess_fp32_d1024_oracle_parity(F, ctx):
     assert nflip <= m // 4
 
 
-@pytest.mark.parametrize("D", [700, 1024])
+@pytest.mark.parametrize("D", [300, 700, 1024])
 def test_ess_first_draw_has_fp32_accuracy(F, ctx, D):
-    """At Dp > 512 the prior and direction products run on the bf16 matrix
+    """At Dp > 256 the prior and direction products run on the bf16 matrix
     cores from exact three-piece splits (six piece products per FP32
     product).  The first draw, x0 cos(theta) + nu sin(theta) with x0 and nu
     both from that product, must match the FP64 oracle to FP32 rounding:
