@@ -5,8 +5,10 @@
 // Kernels:
 //   * nu_gemm_mfma_kernel: ellipse directions nu = L z for a window of
 //     (chain, draw) columns; z is drawn inside the kernel from the Philox
-//     stream of its (chain, draw), L is the triangular prior factor, the
-//     product runs on FP32 MFMA (32x32x2) with FP32 accumulation.
+//     stream of its (chain, draw), L is the triangular prior factor; the
+//     product runs on FP32 MFMA (32x32x2) for Dp <= 256 and, above, on the
+//     bf16 MFMA (32x32x16) from exact three-piece bf16 splits of z and L (six
+//     piece products per FP32 product), FP32 accumulation in both.
 //   * nu_gemm_simple_kernel: the same product in plain FMA (FP64 jobs).
 //   * ess_fsm_kernel: one wavefront per chain; the chain steps through its
 //     FSM for every draw of its window without waiting for any other chain.

@@ -208,20 +208,21 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // accuracy at 6 bf16 products per FP32 product (the bf16 cores run 16 times
 // the FP32 MFMA rate).
 // One block of 8 waves computes 64 columns (col0 ..) over all Dp rows; wave w
-// owns 4 row tiles in snake order (last row tile first, so the tiles that
-// reach K chunk k are a prefix).  Per chunk of 32 k: the z pieces come from
-// LDS ([piece][column][k], rows padded to 40 halfwords so the 16-byte reads
-// do not conflict), the thread draws its 4 normals of the next chunk and
-// stores their pieces in the other LDS buffer, and the (tile, k-block) pairs
-// run in order with the next pair's L pieces in flight -- the last pair loads
-// the next chunk's first one.  L's pieces are packed so that one pair's are
-// contiguous: for row tile ti, chunk c <= ti, k-block kb and piece p, the
-// 32 x 16 block L[32 ti + r][32 c + 16 kb + kk] is 512 halfwords [r][kk] at
-// ((ti (ti + 1) / 2 + c) 2 + kb) 3 + p blocks (each load fills whole lines).  The products
-// and their order per output element do not depend on this scheduling.  A
-// block whose columns are all past their chain's last draw exits at once.
-// The directions are written with nontemporal stores (they are read once, by
-// the next window's kernel), which keeps L's planes in L2.
+// owns RT row tiles in snake order (visited from the last one down, so the
+// tiles that reach K chunk k are a prefix).  Per chunk of 32 k: the z pieces
+// come from LDS ([piece][column][k], rows padded to 40 halfwords so the
+// 16-byte reads do not conflict), the thread draws its 4 normals of the next
+// chunk and stores their pieces in the other LDS buffer, and the (tile,
+// k-block) pairs run in order with the next pair's L pieces in flight -- the
+// last pair loads the next chunk's first one.  L's pieces are packed so that
+// one pair's are contiguous: for row tile ti, chunk c <= ti, k-block kb and
+// piece p, the 32 x 16 block L[32 ti + r][32 c + 16 kb + kk] is the 512
+// halfwords [r][kk] of block ((ti (ti + 1) / 2 + c) 2 + kb) 3 + p, so each
+// load fills whole lines.  The products and their order per output element
+// do not depend on this scheduling.  A block whose columns are all past their
+// chain's last draw exits at once.  The directions are written with
+// nontemporal stores (they are read once, by the next window's kernel), which
+// keeps L's pieces in L2.
 template <int RT, int CT = 2>
 __device__ __forceinline__ void nu_gemm_block_bf16(const NuK<float>& a, int col0)
 {
