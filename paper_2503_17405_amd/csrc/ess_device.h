@@ -209,12 +209,13 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // the FP32 MFMA rate).
 // One block of 8 waves computes 64 columns (col0 ..) over all Dp rows; wave w
 // owns RT row tiles in snake order (visited from the last one down, so the
-// tiles that reach K chunk k are a prefix).  Per chunk of 32 k: the z pieces
-// come from LDS ([piece][column][k], rows padded to 40 halfwords so the
-// 16-byte reads do not conflict), the thread draws its 4 normals of the next
-// chunk and stores their pieces in the other LDS buffer, and the (tile,
-// k-block) pairs run in order with the next pair's L pieces in flight -- the
-// last pair loads the next chunk's first one.  L's pieces are packed so that
+// tiles that reach K chunk k are a prefix).  The z pieces of 4 chunks of 32 k
+// sit in one of two LDS buffers ([piece][column][k], rows padded to 136
+// halfwords so the 16-byte reads do not conflict), so the block meets at a
+// barrier once per 128 k.  Per chunk: the thread draws its 4 normals of the
+// same chunk of the next 128 and stores their pieces in the other buffer, and
+// the (tile, k-block) pairs run in order with the next pair's L pieces in
+// flight -- the last pair loads the next chunk's first one.  L's pieces are packed so that
 // one pair's are contiguous: for row tile ti, chunk c <= ti, k-block kb and
 // piece p, the 32 x 16 block L[32 ti + r][32 c + 16 kb + kk] is the 512
 // halfwords [r][kk] of block ((ti (ti + 1) / 2 + c) 2 + kb) 3 + p, so each
@@ -227,7 +228,7 @@ template <int RT, int CT = 2>
 __device__ __forceinline__ void nu_gemm_block_bf16(const NuK<float>& a, int col0)
 {
     static_assert(CT == 2, "64 columns per block");
-    constexpr int NC = 32 * CT, KR = 40;
+    constexpr int NC = 32 * CT, SUB = 4, KS = 32 * SUB, KR = KS + 8;
     __shared__ uint16_t Zs[2][3][NC][KR];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, l32 = lane & 31;
@@ -250,8 +251,9 @@ __device__ __forceinline__ void nu_gemm_block_bf16(const NuK<float>& a, int col0
     if (!__syncthreads_or(zvalid ? 1 : 0)) return;
 
     // this thread's 4 normals (rows kc + 4 zb .. + 3 of column zc; 0 past D or
-    // for a missing column), split, as 4 consecutive k in each piece plane
-    auto draw_put = [&](int kc, int buf) {
+    // for a missing column), split, as 4 consecutive k (from koff) in each
+    // piece plane of buffer buf
+    auto draw_put = [&](int kc, int buf, int koff) {
         const int kb = kc + 4 * zb;
         float z[4];
         normals4<float>(a.seed, (uint32_t)zchain, zdraw, a.role, 0, (uint32_t)(kb >> 2), z);
@@ -267,7 +269,7 @@ __device__ __forceinline__ void nu_gemm_block_bf16(const NuK<float>& a, int col0
             }
 #pragma unroll
             for (int q = 0; q < 3; ++q)
-                *reinterpret_cast<uint32_t*>(&Zs[buf][q][zc][4 * zb + i]) = pc[0][q] | (pc[1][q] << 16);
+                *reinterpret_cast<uint32_t*>(&Zs[buf][q][zc][koff + 4 * zb + i]) = pc[0][q] | (pc[1][q] << 16);
         }
     };
 
@@ -306,7 +308,9 @@ __device__ __forceinline__ void nu_gemm_block_bf16(const NuK<float>& a, int col0
         for (int p = 0; p < 3; ++p) lr[p] = *reinterpret_cast<const u32x4*>(base + 512 * p);
     };
 
-    draw_put(0, 0);
+#pragma unroll
+    for (int p = 0; p < SUB; ++p)
+        if (32 * p < a.Dp) draw_put(32 * p, 0, 32 * p);
     const int t0row = tiles[0] >= 0 ? tiles[0] : 0;  // a valid row tile for the address
     u32x4 lb[2][3];
     load_l(lb[0], t0row, 0);
@@ -314,11 +318,12 @@ __device__ __forceinline__ void nu_gemm_block_bf16(const NuK<float>& a, int col0
     int buf = 0;
     for (int kc = 0; kc < a.Dp; kc += 32) {
         const bool more = kc + 32 < a.Dp;
+        const int sub = (kc >> 5) & (SUB - 1);  // the chunk's place in its 128 k
         int na = 0;  // tiles that reach this chunk: tiles[0 .. na-1]
 #pragma unroll
         for (int r = 0; r < RT; ++r) na += (tiles[r] >= 0 && 32 * tiles[r] + 31 >= kc) ? 1 : 0;
         na = uni(na);
-        if (more) draw_put(kc + 32, buf ^ 1);
+        if (kc + KS < a.Dp) draw_put(kc + KS, buf ^ 1, 32 * sub);
         // za[kb][c][p]: piece p of z rows kc + 16 kb + 8 h .. + 7, column 32 c + l32
         u32x4 za[2][CT][3];
 #pragma unroll
@@ -327,7 +332,7 @@ __device__ __forceinline__ void nu_gemm_block_bf16(const NuK<float>& a, int col0
             for (int c = 0; c < CT; ++c)
 #pragma unroll
                 for (int p = 0; p < 3; ++p)
-                    za[kb][c][p] = *reinterpret_cast<const u32x4*>(&Zs[buf][p][32 * c + l32][16 * kb + 8 * h]);
+                    za[kb][c][p] = *reinterpret_cast<const u32x4*>(&Zs[buf][p][32 * c + l32][32 * sub + 16 * kb + 8 * h]);
         // pair q = (tile q / 2, k-block q % 2) uses lb[q % 2] and loads pair q + 1
 #pragma unroll
         for (int q = 0; q < 2 * RT; ++q) {
@@ -357,8 +362,10 @@ __device__ __forceinline__ void nu_gemm_block_bf16(const NuK<float>& a, int col0
                 acc[r][c] = t;
             }
         }
-        __syncthreads();
-        buf ^= 1;
+        if (sub == SUB - 1 || !more) {  // the other buffer holds the next 128 k
+            __syncthreads();
+            buf ^= 1;
+        }
     }
     // column g = chain * W + w is stored at out[g * Dp + row]
 #pragma unroll
