@@ -113,6 +113,34 @@ void orc_normals(uint64_t seed, uint32_t chain, uint32_t draw, uint32_t role, ui
 }
 
 /* ------------------------------------------------------------------ */
+/* Optional record of the branch decisions of one draw (test support; the
+ * arithmetic is the same with or without it).  Every floating-point
+ * comparison that picks a branch goes through decide(): with a record
+ * attached it stores the distance of the compared quantity from its
+ * threshold and the magnitude of the terms that quantity was formed from,
+ * and it can invert the outcome of decision number flip_at, so the tests can
+ * replay a draw as if one comparison had gone the other way.             */
+typedef struct {
+    double* margin;
+    double* scale;
+    int32_t cap, n;
+    int32_t flip_at; /* index of the decision to invert, -1 for none */
+} orc_trace;
+
+static __thread orc_trace* g_trace = NULL;
+
+static int decide(int outcome, double margin, double scale)
+{
+    if (!g_trace) return outcome;
+    int32_t i = g_trace->n++;
+    if (i < g_trace->cap) {
+        g_trace->margin[i] = fabs(margin);
+        g_trace->scale[i] = fabs(scale);
+    }
+    return (i == g_trace->flip_at) ? !outcome : outcome;
+}
+
+/* ------------------------------------------------------------------ */
 /* Targets.                                                            */
 enum { ORC_GP_GAUSS = 0, ORC_GP_LOGISTIC = 1, ORC_LOGREG = 2, ORC_FUNNEL = 3, ORC_GAUSS_DIAG = 4 };
 
@@ -148,6 +176,22 @@ double orc_gp_loglik(const orc_target* t, const double* f)
         }
     } else {
         for (int i = 0; i < t->dim; ++i) s += t->y[i] * f[i] - softplus(f[i]);
+    }
+    return s;
+}
+
+/* Sum of the absolute values of the summands of orc_gp_loglik at f. */
+static double gp_loglik_absterms(const orc_target* t, const double* f)
+{
+    double s = 0.0;
+    if (t->kind == ORC_GP_GAUSS) {
+        double inv2v = 1.0 / (2.0 * t->noise_sd * t->noise_sd);
+        for (int i = 0; i < t->dim; ++i) {
+            double r = t->y[i] - f[i];
+            s += r * r * inv2v;
+        }
+    } else {
+        for (int i = 0; i < t->dim; ++i) s += fabs(t->y[i] * f[i]) + softplus(f[i]);
     }
     return s;
 }
@@ -255,13 +299,13 @@ int orc_ess_sample(const orc_target* t, const double* L, uint64_t seed, uint32_t
         for (int i = 0; i < D; ++i) xp[i] = x[i] * c + nu[i] * s;
         double lp = orc_gp_loglik(t, xp);
         ++evals;
-        if (lp > logy) {
+        if (decide(lp > logy, lp - logy, g_trace ? gp_loglik_absterms(t, xp) + fabs(logy) : 0.0)) {
             memcpy(x, xp, sizeof(double) * (size_t)D);
             *lx = lp;
             return evals;
         }
         if (evals >= ORC_ESS_MAX_EVALS) return -evals;
-        if (theta < 0.0)
+        if (decide(theta < 0.0, theta, fabs(tmin) + fabs(tmax)))
             tmin = theta;
         else
             tmax = theta;
@@ -431,6 +475,22 @@ static double dr_log_alpha_stage(int s, int D, const double* scales, const doubl
     return orc_dr_log_alpha3(lx, l1, l2, l3, q);
 }
 
+/* Magnitude of the log terms that the stage-s acceptance is formed from:
+ * |log pi| of x and of the proposals so far, and |log q| of every proposal
+ * density that alpha_s uses.  Used only for a decision record.          */
+static double dr_stage_absterms(int s, int D, const double* scales, const double* x,
+                                const double* y1, const double* y2, const double* y3, double lx,
+                                const double* l)
+{
+    double a = fabs(lx);
+    for (int i = 0; i <= s; ++i) a += fabs(l[i]);
+    if (s >= 1) a += fabs(lq_gauss(x, y1, D, scales[0])) + fabs(lq_gauss(y2, y1, D, scales[0]));
+    if (s >= 2)
+        a += fabs(lq_gauss(x, y2, D, scales[1])) + fabs(lq_gauss(y3, y2, D, scales[0])) +
+             fabs(lq_gauss(y3, y1, D, scales[1])) + fabs(lq_gauss(y1, y2, D, scales[0]));
+    return a;
+}
+
 /* One DR draw.  Returns the number of stages evaluated (1..n_stages);
  * x, lx updated on acceptance.  work: 3*D.                               */
 int orc_dr_sample(const orc_target* t, int n_stages, const double* scales, uint64_t seed,
@@ -445,8 +505,9 @@ int orc_dr_sample(const orc_target* t, int n_stages, const double* scales, uint6
         l[s] = orc_logpdf(t, y[s]);
         double la = dr_log_alpha_stage(s, D, scales, x, y[0], y[1], y[2], *lx, l[0], l[1], l[2]);
         double u = orc_uniform(seed, chain, draw, ORC_ROLE_ACC, (uint32_t)s);
+        double sc = g_trace ? dr_stage_absterms(s, D, scales, x, y[0], y[1], y[2], *lx, l) : 0.0;
         ++s;
-        if (log(u) < la) {
+        if (decide(log(u) < la, log(u) - la, sc)) {
             memcpy(x, y[s - 1], sizeof(double) * (size_t)D);
             *lx = l[s - 1];
             break;
@@ -573,26 +634,6 @@ double orc_leapfrog(const orc_target* t, double veps, double* th, double* p, dou
     return U;
 }
 
-/* Optional record of every branch decision of a NUTS draw: the distance of
- * the compared quantity from its threshold and the magnitude of the terms
- * it was computed from (used by the tests to classify near-ties). */
-typedef struct {
-    double* margin;
-    double* scale;
-    int32_t cap, n;
-} orc_trace;
-
-static __thread orc_trace* g_trace = NULL;
-
-static void trace(double margin, double scale)
-{
-    if (g_trace && g_trace->n < g_trace->cap) {
-        g_trace->margin[g_trace->n] = fabs(margin);
-        g_trace->scale[g_trace->n] = fabs(scale);
-        g_trace->n++;
-    }
-}
-
 static double abs_dot(const double* a, const double* b, int D)
 {
     double s = 0.0;
@@ -616,11 +657,10 @@ static int nuts_leaf_uturn(int D, int j, uint32_t n, const double* p, const doub
     for (int k = 1; k <= j; ++k) {
         if (((n + 1u) & ((1u << k) - 1u)) == 0u) {
             for (int i = 0; i < D; ++i) tmp[i] = rhoS[i] - ckr[(size_t)k * D + i];
-            if (g_trace) {
-                trace(dot(ckp + (size_t)k * D, tmp, D), abs_dot(ckp + (size_t)k * D, tmp, D));
-                trace(dot(p, tmp, D), abs_dot(p, tmp, D));
-            }
-            if (dot(ckp + (size_t)k * D, tmp, D) <= 0.0 || dot(p, tmp, D) <= 0.0) turn = 1;
+            double d0 = dot(ckp + (size_t)k * D, tmp, D), d1 = dot(p, tmp, D);
+            int t0 = decide(d0 <= 0.0, d0, g_trace ? abs_dot(ckp + (size_t)k * D, tmp, D) : 0.0);
+            int t1 = decide(d1 <= 0.0, d1, g_trace ? abs_dot(p, tmp, D) : 0.0);
+            if (t0 || t1) turn = 1;
         }
     }
     return turn;
@@ -692,17 +732,16 @@ int orc_nuts_sample(const orc_target* t, double eps, int max_depth, uint64_t see
             ++nleap;
             double wn = H0 - (Un + 0.5 * dot(pe, pe, D));
             const double escale = fabs(H0) + fabs(Un) + 0.5 * dot(pe, pe, D);
-            trace(-wn - ORC_NUTS_DMAX, escale);
-            if (!(-wn <= ORC_NUTS_DMAX)) {
+            if (decide(!(-wn <= ORC_NUTS_DMAX), -wn - ORC_NUTS_DMAX, escale)) {
                 invalid = 1;
                 diverged = 1;
                 break;
             }
             double Wn = logaddexp(Ws, wn);
-            if (n > 0)
-                trace(log(orc_uniform(seed, chain, draw, ORC_ROLE_LEAF, ((uint32_t)j << 16) | n)) - (wn - Wn),
-                      escale);
-            if (log(orc_uniform(seed, chain, draw, ORC_ROLE_LEAF, ((uint32_t)j << 16) | n)) < wn - Wn) {
+            double lu = log(orc_uniform(seed, chain, draw, ORC_ROLE_LEAF, ((uint32_t)j << 16) | n));
+            /* the first leaf of a subtree is always taken (wn - Wn = 0 > lu):
+             * not a decision that rounding can invert, so it is not recorded */
+            if (n == 0 ? (lu < wn - Wn) : decide(lu < wn - Wn, lu - (wn - Wn), escale)) {
                 memcpy(w.thS, the, sizeof(double) * D);
                 memcpy(w.gS, ge, sizeof(double) * D);
                 w.US = Un;
@@ -720,19 +759,18 @@ int orc_nuts_sample(const orc_target* t, double eps, int max_depth, uint64_t see
         if (invalid) {
             stop = 1;
         } else {
-            trace(log(orc_uniform(seed, chain, draw, ORC_ROLE_MERGE, (uint32_t)j)) - (Ws - W), fabs(H0) + 1.0);
-            if (log(orc_uniform(seed, chain, draw, ORC_ROLE_MERGE, (uint32_t)j)) < Ws - W) {
+            double lu = log(orc_uniform(seed, chain, draw, ORC_ROLE_MERGE, (uint32_t)j));
+            if (decide(lu < Ws - W, lu - (Ws - W), fabs(H0) + 1.0)) {
                 memcpy(w.thP, w.thS, sizeof(double) * D);
                 memcpy(w.gP, w.gS, sizeof(double) * D);
                 w.UP = w.US;
             }
             W = logaddexp(W, Ws);
             for (int i = 0; i < D; ++i) w.rho[i] += w.rhoS[i];
-            if (g_trace) {
-                trace(dot(w.pL, w.rho, D), abs_dot(w.pL, w.rho, D));
-                trace(dot(w.pR, w.rho, D), abs_dot(w.pR, w.rho, D));
-            }
-            if (dot(w.pL, w.rho, D) <= 0.0 || dot(w.pR, w.rho, D) <= 0.0) {
+            double dl = dot(w.pL, w.rho, D), dr = dot(w.pR, w.rho, D);
+            int tl = decide(dl <= 0.0, dl, g_trace ? abs_dot(w.pL, w.rho, D) : 0.0);
+            int tr = decide(dr <= 0.0, dr, g_trace ? abs_dot(w.pR, w.rho, D) : 0.0);
+            if (tl || tr) {
                 stop = 1;
                 turned = 1;
             }
@@ -1034,17 +1072,44 @@ int orc_run_chain(const orc_target* t, const orc_sampler* sp, uint64_t seed, uin
     return guards;
 }
 
-/* orc_nuts_sample with every branch decision recorded into (margin, scale)
- * arrays of capacity cap; returns the number of leapfrogs, *n_dec the number
- * of decisions recorded. */
-int orc_nuts_sample_traced(const orc_target* t, double eps, int max_depth, uint64_t seed,
-                           uint32_t chain, uint32_t draw, double* th, double* U, double* g,
-                           double* wsbuf, orc_nuts_info* info, double* margin, double* scale,
-                           int32_t cap, int32_t* n_dec)
+/*
+ * One draw of any sampler from the state x (in/out), with its branch
+ * decisions recorded into (margin, scale) arrays of capacity cap and, if
+ * flip_at >= 0, decision number flip_at inverted.  The cached quantities
+ * (log L(x), or U and grad U) are recomputed from x.  Returns the loop count
+ * of the draw (ESS: evaluations, negative if the guard tripped; NUTS:
+ * leapfrogs; DR: stages), or 0 on a bad argument; *n_dec is the number of
+ * decisions taken.
+ */
+int orc_draw_traced(const orc_target* t, const orc_sampler* sp, uint64_t seed, uint32_t chain,
+                    uint32_t draw, double* x, double* margin, double* scale, int32_t cap,
+                    int32_t* n_dec, int32_t flip_at)
 {
-    orc_trace tr = {margin, scale, cap, 0};
+    int D = t->dim;
+    if (D <= 0) return 0;
+    orc_trace tr = {margin, scale, cap, 0, flip_at};
+    int r = 0;
     g_trace = &tr;
-    int r = orc_nuts_sample(t, eps, max_depth, seed, chain, draw, th, U, g, wsbuf, info);
+    if (sp->kind == ORC_ESS) {
+        double* work = (double*)calloc((size_t)D * 3, sizeof(double));
+        double lx = orc_gp_loglik(t, x);
+        r = orc_ess_sample(t, sp->chol_L, seed, chain, draw, x, &lx, work);
+        free(work);
+    } else if (sp->kind == ORC_DRMH) {
+        double* work = (double*)calloc((size_t)D * 3, sizeof(double));
+        double lx = orc_logpdf(t, x);
+        r = orc_dr_sample(t, sp->n_stages, sp->scales, seed, chain, draw, x, &lx, work);
+        free(work);
+    } else if (sp->kind == ORC_NUTS && sp->max_depth >= 1 && sp->max_depth <= ORC_NUTS_MAXJ) {
+        /* zeroed: a replay with an inverted decision may read a slot that the
+         * uninverted draw always writes first */
+        double* buf = (double*)calloc((size_t)D + nuts_ws_len(D), sizeof(double));
+        double *g = buf, *wsb = buf + D;
+        double U = orc_potential(t, x, g);
+        orc_nuts_info info;
+        r = orc_nuts_sample(t, sp->step_size, sp->max_depth, seed, chain, draw, x, &U, g, wsb, &info);
+        free(buf);
+    }
     g_trace = NULL;
     *n_dec = tr.n;
     return r;

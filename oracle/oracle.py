@@ -96,8 +96,8 @@ def lib():
             L.orc_nuts_subtree_first_turn.argtypes = [i32, i32, p]
             L.orc_nuts_sample.restype = i32
             L.orc_nuts_sample.argtypes = [p, d, i32, u64, u32, u32, p, p, p, p, p]
-            L.orc_nuts_sample_traced.restype = i32
-            L.orc_nuts_sample_traced.argtypes = [p, d, i32, u64, u32, u32, p, p, p, p, p, p, p, i32, p]
+            L.orc_draw_traced.restype = i32
+            L.orc_draw_traced.argtypes = [p, p, u64, u32, u32, p, p, p, i32, p, i32]
             L.orc_ess_sample.restype = i32
             L.orc_ess_sample.argtypes = [p, p, u64, u32, u32, p, p, p]
             L.orc_dr_sample.restype = i32
@@ -264,20 +264,21 @@ def nuts_sample(target, eps, max_depth, seed, chain, draw, th, U, g):
                                   diverged=info.diverged, turned=info.turned)
 
 
-def nuts_decisions(target, eps, max_depth, seed, chain, draw, th, cap=1 << 16):
-    """Branch decisions of one NUTS draw from state th: arrays (margin, scale)."""
-    D = target.dim
-    th = _f64(th).copy()
-    U, g = potential(target, th, grad=True)
-    Uc = C.c_double(U)
-    ws = np.zeros(D * (13 + 2 * 16))
-    info = _NutsInfo()
+def draw_traced(target, sampler, seed, chain, draw, x_prev, flip_at=-1, cap=1 << 16):
+    """One draw from x_prev with its branch decisions recorded; with
+    flip_at >= 0 the outcome of decision number flip_at is inverted.
+    Returns (x, loop count, margins, scales): margin k is the distance of
+    decision k's compared quantity from its threshold, scale k the magnitude
+    of the terms it was formed from."""
+    x = _f64(x_prev).copy()
     mar, sca = np.zeros(cap), np.zeros(cap)
     nd = C.c_int32()
-    lib().orc_nuts_sample_traced(target.ref, float(eps), int(max_depth), seed, chain, draw, _ptr(th),
-                                 C.byref(Uc), _ptr(g), _ptr(ws), C.byref(info), _ptr(mar), _ptr(sca),
-                                 cap, C.byref(nd))
-    return mar[:nd.value], sca[:nd.value]
+    cnt = lib().orc_draw_traced(target.ref, sampler.ref, seed, chain, draw, _ptr(x), _ptr(mar),
+                                _ptr(sca), cap, C.byref(nd), int(flip_at))
+    if cnt == 0:
+        raise ValueError("oracle rejected the arguments")
+    k = min(nd.value, cap)
+    return x, abs(int(cnt)), mar[:k], sca[:k]
 
 
 def ess_init(chol_L, seed, chain):

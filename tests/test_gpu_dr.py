@@ -66,19 +66,13 @@ def test_dr_oracle_parity(F, ctx, kind):
         tg = O.gauss_target(prec.astype(np.float32).astype(np.float64))
     S, C, _ = gpu_dr(F, ctx, tg_gpu, m, n, seed, scales)
     R, RC, _ = O.run_chains(tg, O.dr_sampler(scales), seed, range(m), n)
-    err, flips = parity.compare_draws(S, R, C, RC, first=n)
-    bad = 0
-    for j in np.nonzero(flips >= 0)[0]:
-        t = int(flips[j])
-        if t > 0:
-            xp = R[j, t - 1]
-        else:
-            xp = O.funnel_init(10, seed, int(j)) if kind == "funnel" else O.normal_init(tg.dim, seed, int(j))
-        near, _ = parity.dr_flip_near_tie(tg, scales, 3, seed, int(j), t, xp)
-        bad += not near
-    print("DR %s: max rel err %.3g, flips %d/%d, not near-tie %d" % (kind, err, (flips >= 0).sum(), m, bad))
-    assert err <= 1e-4
-    assert bad == 0
+    init = (lambda j: O.funnel_init(10, seed, j)) if kind == "funnel" else (lambda j: O.normal_init(tg.dim, seed, j))
+    x_init = np.array([init(j) for j in range(m)])
+    r = parity.check_chains(S, C, R, RC, tg, O.dr_sampler(scales), seed, range(m), x_init, first=n)
+    print(parity.summary("DR %s" % kind, r))
+    assert r["worst"] <= 1e-4
+    assert not r["bad"]
+    assert r["flip_frac"] <= 0.1
 
 
 def test_dr_one_stage_and_explicit_start(F, ctx):
@@ -89,9 +83,9 @@ def test_dr_one_stage_and_explicit_start(F, ctx):
     x0 = x0.astype(np.float32).astype(np.float64)
     S, C, _ = gpu_dr(F, ctx, tg_gpu, 33, 80, 4, scales=(0.8,), x0=x0)
     R, RC, _ = O.run_chains(tg, O.dr_sampler((0.8,)), 4, range(33), 80, x0=x0)
-    err, flips = parity.compare_draws(S, R, C, RC, first=80)
+    r = parity.check_chains(S, C, R, RC, tg, O.dr_sampler((0.8,)), 4, range(33), x0, first=80)
     assert np.all(C == 1)
-    assert err <= 1e-4 and (flips >= 0).sum() <= 1
+    assert r["worst"] <= 1e-4 and not r["bad"] and r["parted"] <= 1
 
 
 def test_dr_gaussian_moments(F, ctx):

@@ -63,14 +63,24 @@ def oracle_ess(w, m, n, seed, noise_sd=None, x0=None):
     return draws, counts, tg
 
 
+def ess_parity(w, S, C, R, RC, seed, chains, noise_sd=None, x0=None, first=100, tol=1e-4):
+    """Per-draw comparison with the oracle; partings must be near-tie flips
+    at the decision where the two runs part."""
+    tg = O.gp_target(w["y"], noise_sd=noise_sd)
+    chains = list(chains)
+    x_init = x0 if x0 is not None else np.array([O.ess_init(w["L"], seed, int(j)) for j in chains])
+    return parity.check_chains(S, C, R, RC, tg, O.ess_sampler(w["L"]), seed, chains, x_init,
+                               first=first, tol=tol)
+
+
 def test_ess_fp64_d16_oracle_parity(F, ctx):
     w = inputs.gp_gauss(dim=16, lengthscale=0.2, jitter=1e-6, noise_sd=0.1, seed=1001)
     S, C, st = gpu_ess(F, ctx, w, 64, 100, 1002, fp64=True, noise_sd=0.1)
     R, RC, _ = oracle_ess(w, 64, 100, 1002, noise_sd=0.1)
-    err, flips = parity.compare_draws(S, R, C, RC, first=100)
-    print("fp64 d16: max rel err %.3g, flips %d" % (err, (flips >= 0).sum()))
-    assert (flips >= 0).sum() == 0
-    assert err <= 1e-10
+    r = ess_parity(w, S, C, R, RC, 1002, range(64), noise_sd=0.1, tol=1e-10)
+    print(parity.summary("fp64 d16", r))
+    assert r["parted"] == 0
+    assert r["worst"] <= 1e-10
     assert st["guard_trips"] == 0 and st["chains_done"] == 64
 
 
@@ -113,20 +123,11 @@ def test_ess_fp32_d1024_oracle_parity(F, ctx):
     m, n, seed = 64, 100, 2002
     S, C, st = gpu_ess(F, ctx, w, m, n, seed)
     R, RC, tg = oracle_ess(w, m, n, seed)
-    err, flips = parity.compare_draws(S, R, C, RC, first=100)
-    nflip = int((flips >= 0).sum())
-    bad = 0
-    for j in np.nonzero(flips >= 0)[0]:
-        t = flips[j]
-        x_prev = R[j, t - 1] if t > 0 else O.ess_init(w["L"], seed, int(j))
-        margin, terms = parity.ess_flip_margin(tg, w["L"], seed, int(j), int(t), x_prev,
-                                               int(C[j, t]), int(RC[j, t]))
-        bad += not parity.is_near_tie(margin, terms)
-    print("fp32 d1024: max rel err %.3g over pre-flip draws; chains with a flip %d/%d, "
-          "not near-tie %d" % (err, nflip, m, bad))
-    assert err <= 1e-4
-    assert bad == 0
-    assert nflip <= m // 4
+    r = ess_parity(w, S, C, R, RC, seed, range(m))
+    print(parity.summary("fp32 d1024", r))
+    assert r["worst"] <= 1e-4
+    assert not r["bad"]
+    assert r["flip_frac"] <= 0.1
 
 
 @pytest.mark.parametrize("D", [300, 700, 1024])
@@ -174,16 +175,10 @@ def test_ess_c2_full_size_sampled_chains_oracle_parity(F, ctx):
     tg = O.gp_target(w["y"])
     R, RC, guards = O.run_chains(tg, O.ess_sampler(w["L"]), seed, idx, first)
     assert guards == 0
-    err, flips = parity.compare_draws(S, R, C[idx], RC, first=first)
-    bad = 0
-    for k in np.nonzero(flips >= 0)[0]:
-        j, t = idx[k], int(flips[k])
-        x_prev = R[k, t - 1] if t > 0 else O.ess_init(w["L"], seed, j)
-        margin, terms = parity.ess_flip_margin(tg, w["L"], seed, j, t, x_prev, int(C[j, t]), int(RC[k, t]))
-        bad += not parity.is_near_tie(margin, terms)
-    print("C2 full size, chains %s: max rel err %.3g, flips %d, not near-tie %d"
-          % (idx, err, int((flips >= 0).sum()), bad))
-    assert err <= 1e-4 and bad == 0
+    r = ess_parity(w, S, C[idx], R, RC, seed, idx, first=first)
+    print(parity.summary("C2 full size, chains %s" % idx, r))
+    assert r["worst"] <= 1e-4 and not r["bad"]
+    assert r["parted"] <= 2
 
 
 @pytest.mark.parametrize("D", [1, 17, 100, 333, 700, 769, 1000])
@@ -192,9 +187,10 @@ def test_ess_ragged_dims_oracle_parity(F, ctx, D):
     m, n = 37, 40
     S, C, _ = gpu_ess(F, ctx, w, m, n, 9)
     R, RC, _ = oracle_ess(w, m, n, 9)
-    err, flips = parity.compare_draws(S, R, C, RC, first=n)
-    assert err <= 1e-4, D
-    assert (flips >= 0).sum() <= 2
+    r = ess_parity(w, S, C, R, RC, 9, range(m), first=n)
+    print(parity.summary("D=%d" % D, r))
+    assert r["worst"] <= 1e-4, D
+    assert not r["bad"] and r["parted"] <= 2
 
 
 def test_ess_explicit_x0(F, ctx):
@@ -202,8 +198,8 @@ def test_ess_explicit_x0(F, ctx):
     x0 = np.random.default_rng(0).standard_normal((12, 64)) * 0.5
     S, C, _ = gpu_ess(F, ctx, w, 12, 30, 4, x0=x0)
     R, RC, _ = oracle_ess(w, 12, 30, 4, x0=x0)
-    err, flips = parity.compare_draws(S, R, C, RC, first=30)
-    assert err <= 1e-4 and (flips >= 0).sum() == 0
+    r = ess_parity(w, S, C, R, RC, 4, range(12), x0=x0, first=30)
+    assert r["worst"] <= 1e-4 and r["parted"] == 0
 
 
 @pytest.mark.parametrize("fp64", [True, False])
@@ -220,8 +216,9 @@ def test_ess_pipelined_windows_equal_sequential(F, ctx, fp64):
     assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
     # draws use distinct ellipse directions: no two draws of a chain repeat a proposal step
     R, RC, _ = oracle_ess(w, 4, 61, 9, noise_sd=noise)
-    err, flips = parity.compare_draws(a[0][:4], R, a[1][:4], RC, first=61)
-    assert err <= (1e-10 if fp64 else 1e-4)
+    r = ess_parity(w, a[0][:4], a[1][:4], R, RC, 9, range(4), noise_sd=noise, first=61,
+                   tol=1e-10 if fp64 else 1e-4)
+    assert r["worst"] <= (1e-10 if fp64 else 1e-4) and not r["bad"]
 
 
 def test_ess_step_budget_semantics(F, ctx):
