@@ -84,3 +84,52 @@ def summary(name, r):
     return ("%s: max rel err %.3g over %d draws; chains parted %d (%.2f%%), all near-tie flips: %s%s"
             % (name, r["worst"], r["compared"], r["parted"], 100 * r["flip_frac"], not r["bad"],
                "" if not r["bad"] else " unexplained %s" % r["bad"][:4]))
+
+
+# ------------------------------------------------ jobs of a batch or server mix
+def oracle_job(spec):
+    """The oracle's (target, sampler, chain seed, initial state of chain j) for
+    a tagged job spec of the batch / serving tests:
+      ("ess", dim, chains, draws, data seed, chain seed)       GP-logistic ESS
+      ("dr", "funnel"|"gauss", dim, chains, draws, seed)       3-stage DR
+      ("nuts", rows, dim, chains, draws, data seed, chain seed, step)
+    The inputs are regenerated from the seeded generators; the Gaussian
+    target's precisions are torch's linspace (what the GPU job was given)."""
+    from paper_2503_17405_amd import inputs
+    kind = spec[0]
+    if kind == "ess":
+        _, D, m, n, ds, cs = spec
+        w = inputs.gp_logistic(dim=D, lengthscale=0.05, jitter=1e-5, seed=ds)
+        return O.gp_target(w["y"]), O.ess_sampler(w["L"]), cs, lambda j: O.ess_init(w["L"], cs, j)
+    if kind == "dr":
+        _, tk, D, m, n, seed = spec
+        if tk == "funnel":
+            return O.funnel_target(D), O.dr_sampler(), seed, lambda j: O.funnel_init(D, seed, j)
+        import torch
+        prec = torch.linspace(0.5, 2.0, D, device="cuda").cpu().numpy().astype(np.float64)
+        return O.gauss_target(prec), O.dr_sampler(), seed, lambda j: O.normal_init(D, seed, j)
+    _, N, D, m, n, ds, cs, eps = spec
+    w = inputs.logreg(n_data=N, dim=D, seed=ds)
+    x0 = inputs.logreg_laplace(w["X"], w["y"], m, seed=ds + 7)["x0"]
+    x0 = x0.astype(np.float32).astype(np.float64)  # the GPU job starts from the FP32 values
+    return (O.logreg_target(w["X"].astype(np.float64), w["y"]), O.nuts_sampler(eps), cs,
+            lambda j: x0[j])
+
+
+def check_job(spec, S, C, chains, first=100, tol=1e-4):
+    """Oracle parity of chains `chains` of one job of a mix; S, C are the
+    job's full (m, n, D) draws and (m, n) loop counts from the GPU."""
+    tg, sp, seed, init = oracle_job(spec)
+    chains = list(chains)
+    x_init = np.array([init(j) for j in chains])
+    n = min(first, S.shape[1])
+    R, RC, _ = O.run_chains(tg, sp, seed, chains, n, x0=x_init)
+    return check_chains(S[chains, :n], C[chains, :n], R, RC, tg, sp, seed, chains, x_init,
+                        first=n, tol=tol)
+
+
+def sample_chains(m, k, seed):
+    """First, last and k-2 random chain indices of an m-chain job."""
+    rest = np.random.default_rng(seed).choice(np.arange(1, max(m - 1, 1)), size=max(0, min(k - 2, m - 2)),
+                                              replace=False) if m > 2 else []
+    return sorted(set([0, m - 1] + [int(i) for i in rest]))

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 import torch
 
+import parity
 from paper_2503_17405_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -153,6 +154,33 @@ def test_batch_with_nuts_jobs(F, ctx, reference):
     finally:
         for j in jobs:
             j.free()
+
+
+def test_batch_mix_oracle_parity(F, ctx):
+    """ESS, DR and NUTS jobs batched together (autotuned): sampled chains of
+    every job against the FP64 oracle over their first 40 draws (1e-4
+    relative; a parting must be the oracle's draw with one near-tie decision
+    inverted)."""
+    specs = ([("ess",) + e for e in ESS_MIX] + [("dr",) + d for d in DR_MIX]
+             + [("nuts",) + x for x in NUTS_MIX])
+    jobs = make_jobs(F, ctx) + nuts_jobs(F, ctx, NUTS_MIX)
+    try:
+        b = F.Batch(ctx, jobs, window=8, dr_chunk=8, nuts_steps=5, autotune=True)
+        assert b.run(0)
+        b.free()
+        res = results(jobs)
+    finally:
+        for j in jobs:
+            j.free()
+    parted = compared = 0
+    for k, (spec, (S, C)) in enumerate(zip(specs, res)):
+        chains = parity.sample_chains(S.shape[0], 4, 100 + k)
+        r = parity.check_job(spec, S, C, chains, first=40)
+        print(parity.summary("batched job %d %s" % (k, spec[:3]), r))
+        assert r["worst"] <= 1e-4 and not r["bad"], (k, spec)
+        parted += r["parted"]
+        compared += len(chains)
+    assert parted <= compared // 10
 
 
 def test_batch_wide_drmh(F, ctx):

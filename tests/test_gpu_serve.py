@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 import torch
 
+import parity
 from paper_2503_17405_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -93,12 +94,17 @@ def reference(F):
         ctx.close()
 
 
-def test_served_mix_equals_alone(F, reference):
+@pytest.fixture(scope="module")
+def served(F):
     ctx = F.Context(0)
     try:
-        got, recs, st = serve(F, ctx, MIX, gaps=[0.0, 0.02, 0.0, 0.05])
+        return serve(F, ctx, MIX, gaps=[0.0, 0.02, 0.0, 0.05])
     finally:
         ctx.close()
+
+
+def test_served_mix_equals_alone(F, reference, served):
+    got, recs, st = served
     for k, ((S, C), (R, RC)) in enumerate(zip(got, reference)):
         assert recs[k]["status"] == F.OK
         assert np.array_equal(C, RC), "job %d counts" % k
@@ -107,6 +113,22 @@ def test_served_mix_equals_alone(F, reference):
     assert st["completed"] == len(MIX) and st["failed"] == 0 and st["live_jobs"] == 0
     print("served %d jobs: %d rounds, %.1f ms on device, peak %d live jobs"
           % (len(MIX), st["rounds"], st["gpu_ms"], st["peak_live_jobs"]))
+
+
+def test_served_mix_oracle_parity(F, served):
+    """Sampled chains of every served job (ESS, DR and NUTS, admitted while
+    others run) against the FP64 oracle over their first 40 draws."""
+    got, recs, _ = served
+    parted = compared = 0
+    for k, (spec, (S, C)) in enumerate(zip(MIX, got)):
+        assert recs[k]["status"] == F.OK
+        chains = parity.sample_chains(S.shape[0], 4, 200 + k)
+        r = parity.check_job(spec, S, C, chains, first=40)
+        print(parity.summary("served job %d %s" % (k, spec[:3]), r))
+        assert r["worst"] <= 1e-4 and not r["bad"], (k, spec)
+        parted += r["parted"]
+        compared += len(chains)
+    assert parted <= compared // 10
 
 
 def test_served_under_budget_and_oversized_job(F, reference):
