@@ -142,16 +142,19 @@ static int decide(int outcome, double margin, double scale)
 
 /* ------------------------------------------------------------------ */
 /* Targets.                                                            */
-enum { ORC_GP_GAUSS = 0, ORC_GP_LOGISTIC = 1, ORC_LOGREG = 2, ORC_FUNNEL = 3, ORC_GAUSS_DIAG = 4 };
+enum { ORC_GP_GAUSS = 0, ORC_GP_LOGISTIC = 1, ORC_LOGREG = 2, ORC_FUNNEL = 3, ORC_GAUSS_DIAG = 4,
+       ORC_MOG = 5 };
 
 typedef struct {
     int32_t kind;
     int32_t dim;
-    int32_t n_data;
+    int32_t n_data;     /* LOGREG: rows of X; MOG: number of components K      */
     int32_t pad_;
-    const double* X;    /* LOGREG: n_data x dim, row-major                    */
-    const double* y;    /* GP: dim observations/labels; LOGREG: n_data labels */
-    const double* prec; /* GAUSS_DIAG: dim precisions                          */
+    const double* X;    /* LOGREG: n_data x dim, row-major; MOG: K x dim means */
+    const double* y;    /* GP: dim observations/labels; LOGREG: n_data labels;
+                           MOG: K log mixture weights                          */
+    const double* prec; /* GAUSS_DIAG: dim precisions; MOG: dim x dim shared
+                           precision matrix (inverse covariance), row-major    */
     double noise_sd;    /* GP_GAUSS observation noise standard deviation       */
 } orc_target;
 
@@ -220,6 +223,43 @@ double orc_potential(const orc_target* t, const double* th, double* g)
             U += 0.5 * t->prec[d] * th[d] * th[d];
             if (g) g[d] = t->prec[d] * th[d];
         }
+    } else if (t->kind == ORC_MOG) {
+        /* Mixture of K Gaussians with one shared covariance (Sec. 7.3):
+         * pi(x) ∝ sum_k w_k exp(-q_k / 2), q_k = (x - mu_k)^T P (x - mu_k).
+         * U = -log sum_k exp(log w_k - q_k / 2), taken relative to the largest
+         * term; grad U = sum_k r_k P (x - mu_k), r_k the component weights. */
+        int K = t->n_data;
+        double* a = (double*)malloc(sizeof(double) * (size_t)K);
+        double* dx = (double*)malloc(sizeof(double) * (size_t)D);
+        double* Pd = (double*)malloc(sizeof(double) * (size_t)D * (size_t)K);
+        double amax = -INFINITY;
+        for (int k = 0; k < K; ++k) {
+            const double* mu = t->X + (size_t)k * D;
+            for (int d = 0; d < D; ++d) dx[d] = th[d] - mu[d];
+            double q = 0.0;
+            for (int i = 0; i < D; ++i) {
+                double s = 0.0;
+                for (int j = 0; j < D; ++j) s += t->prec[(size_t)i * D + j] * dx[j];
+                Pd[(size_t)k * D + i] = s;
+                q += dx[i] * s;
+            }
+            a[k] = t->y[k] - 0.5 * q;
+            if (a[k] > amax) amax = a[k];
+        }
+        double z = 0.0;
+        for (int k = 0; k < K; ++k) z += exp(a[k] - amax);
+        double lse = amax + log(z);
+        U = -lse;
+        if (g) {
+            for (int d = 0; d < D; ++d) g[d] = 0.0;
+            for (int k = 0; k < K; ++k) {
+                double r = exp(a[k] - lse);
+                for (int d = 0; d < D; ++d) g[d] += r * Pd[(size_t)k * D + d];
+            }
+        }
+        free(a);
+        free(dx);
+        free(Pd);
     } else if (t->kind == ORC_FUNNEL) {
         /* Neal's funnel: v ~ N(0, 9), x_i | v ~ N(0, e^v), i = 1..D-1. */
         double v = th[0], ss = 0.0;
@@ -690,6 +730,10 @@ typedef struct {
     int32_t depth;     /* number of subtrees built */
     int32_t diverged;
     int32_t turned;
+    double accept;     /* sum over the draw's leapfrogs of min(1, exp(H0 - H)),
+                          a divergent or undefined energy counting 0: the
+                          acceptance statistic that step-size adaptation
+                          targets (Hoffman & Gelman 2014, Sec. 3.2)       */
 } orc_nuts_info;
 
 /* One NUTS draw as nested while loops.  th, U, g: current state (g = grad U
@@ -715,7 +759,7 @@ int orc_nuts_sample(const orc_target* t, double eps, int max_depth, uint64_t see
     memcpy(w.thP, th, sizeof(double) * D);
     memcpy(w.gP, g, sizeof(double) * D);
     w.UP = *U;
-    double W = 0.0;
+    double W = 0.0, acc = 0.0;
     int j = 0, stop = 0, nleap = 0, diverged = 0, turned = 0;
 
     while (!stop && j < max_depth) {
@@ -731,6 +775,10 @@ int orc_nuts_sample(const orc_target* t, double eps, int max_depth, uint64_t see
             double Un = orc_leapfrog(t, v * eps, the, pe, ge, w.ph);
             ++nleap;
             double wn = H0 - (Un + 0.5 * dot(pe, pe, D));
+            if (wn >= 0.0)
+                acc += 1.0;
+            else if (wn > -INFINITY)
+                acc += exp(wn);
             const double escale = fabs(H0) + fabs(Un) + 0.5 * dot(pe, pe, D);
             if (decide(!(-wn <= ORC_NUTS_DMAX), -wn - ORC_NUTS_DMAX, escale)) {
                 invalid = 1;
@@ -786,6 +834,7 @@ int orc_nuts_sample(const orc_target* t, double eps, int max_depth, uint64_t see
         info->depth = j;
         info->diverged = diverged;
         info->turned = turned;
+        info->accept = acc;
     }
     return nleap;
 }

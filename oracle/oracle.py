@@ -22,7 +22,7 @@ _SRC = os.path.join(_HERE, "fsmmc_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # target kinds
-GP_GAUSS, GP_LOGISTIC, LOGREG, FUNNEL, GAUSS_DIAG = 0, 1, 2, 3, 4
+GP_GAUSS, GP_LOGISTIC, LOGREG, FUNNEL, GAUSS_DIAG, MOG = 0, 1, 2, 3, 4, 5
 # sampler kinds
 ESS, NUTS, DRMH = 0, 1, 2
 # stream roles
@@ -55,7 +55,7 @@ class _Sampler(C.Structure):
 
 class _NutsInfo(C.Structure):
     _fields_ = [("n_leapfrog", C.c_int32), ("depth", C.c_int32), ("diverged", C.c_int32),
-                ("turned", C.c_int32)]
+                ("turned", C.c_int32), ("accept", C.c_double)]
 
 
 _lib = None
@@ -149,6 +149,14 @@ def logreg_target(X, y):
 
 def funnel_target(dim=10):
     return Target(FUNNEL, dim)
+
+
+def mog_target(means, log_weights, prec):
+    """Mixture of K Gaussians sharing one precision matrix P (Sec. 7.3):
+    pi(x) ∝ sum_k w_k exp(-(x - mu_k)^T P (x - mu_k) / 2).  means (K, D)."""
+    means = np.atleast_2d(np.asarray(means, dtype=np.float64))
+    return Target(MOG, means.shape[1], X=means, y=np.asarray(log_weights, dtype=np.float64),
+                  prec=np.asarray(prec, dtype=np.float64))
 
 
 def gauss_target(prec):
@@ -261,7 +269,7 @@ def nuts_sample(target, eps, max_depth, seed, chain, draw, th, U, g):
     lib().orc_nuts_sample(target.ref, float(eps), int(max_depth), seed, chain, draw, _ptr(th),
                           C.byref(Uc), _ptr(g), _ptr(ws), C.byref(info))
     return th, Uc.value, g, dict(n_leapfrog=info.n_leapfrog, depth=info.depth,
-                                  diverged=info.diverged, turned=info.turned)
+                                  diverged=info.diverged, turned=info.turned, accept=info.accept)
 
 
 def draw_traced(target, sampler, seed, chain, draw, x_prev, flip_at=-1, cap=1 << 16):

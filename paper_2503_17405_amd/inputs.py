@@ -14,6 +14,13 @@ Workload recipes (the sizes the benchmark and tests use):
   * ``logreg``: X (N x D) i.i.d. N(0, 1) in FP32, beta_true ~ N(0, I),
     y ~ Bern(sigmoid(X beta_true)); optional Laplace-approximation starting
     points beta0 ~ N(beta_MAP, H^-1), H = X^T W X + I.
+  * ``mog``: the correlated mixture of Gaussians of the NUTS experiment:
+    D-dimensional, one covariance Sigma = (1 - rho) I + rho 1 1^T shared by K
+    equally weighted components whose means sit at c 1 for c in ``modes``
+    (along the principal direction 1 / sqrt(D)); the precision matrix
+    Sigma^-1, the means and the log weights are rounded to FP32 so that every
+    side reads the same numbers; starting points are exact draws from the
+    mixture.
 """
 from __future__ import annotations
 
@@ -101,3 +108,25 @@ def ess_uneven_targets(n_targets=32, dmin=64, dmax=1024, mmin=256, mmax=2048, nm
         out.append(dict(dim=D, n_chains=m, n_draws=n, data_seed=int(g.integers(1 << 31)),
                         chain_seed=int(g.integers(1 << 62))))
     return out
+
+
+def mog(dim=100, rho=0.99, modes=(-10.0, 0.0, 10.0), n_chains=0, seed=6001):
+    """Correlated mixture of Gaussians; x0: n_chains exact draws (or None)."""
+    D, K = int(dim), len(modes)
+    cov = (1.0 - rho) * np.eye(D) + rho * np.ones((D, D))
+    prec = np.linalg.inv(cov)
+    prec = 0.5 * (prec + prec.T)
+    prec32 = prec.astype(np.float32)
+    means = np.array([[c] * D for c in modes], dtype=np.float32)
+    logw = np.full(K, np.log(1.0 / K), dtype=np.float32)
+    # the covariance the rounded precision defines (both sides sample that target)
+    cov_r = np.linalg.inv(prec32.astype(np.float64))
+    cov_r = 0.5 * (cov_r + cov_r.T)
+    x0 = None
+    if n_chains > 0:
+        g = _rng(seed)
+        comp = g.integers(0, K, size=n_chains)
+        Lc = np.linalg.cholesky(cov_r)
+        Z = g.standard_normal((n_chains, D))
+        x0 = np.ascontiguousarray(means.astype(np.float64)[comp] + Z @ Lc.T)
+    return dict(prec=prec32, means=means, log_weights=logw, cov=cov_r, x0=x0, rho=rho, modes=tuple(modes))
