@@ -202,6 +202,32 @@ fsmmc_status fsmmc_collect_counts(fsmmc_job* job, int32_t* dst);
 fsmmc_status fsmmc_eval_potential(fsmmc_job* job, int32_t n_points, const void* theta, void* grad,
                                   void* U);
 
+/* Size of the device workspace of fsmmc_eval_potential_noalloc: one fixed
+ * array per device, held from the first context on that device until the
+ * process ends. */
+#define FSMMC_NOALLOC_SCRATCH_BYTES (8u << 20)
+
+/* fsmmc_eval_potential for callers that cannot allocate device memory (code
+ * under stream or graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same bits, but the padded results go
+ * through the library's fixed per-device workspace instead of buffers
+ * allocated per call, and the call does not synchronise.
+ *   theta: device, n_points x dim positions (n_points <= n_chains);
+ *   grad:  device, n_points x dim output, or NULL;
+ *   U:     device, n_points output.
+ * Everything is queued on the job's stream; the outputs are ready when that
+ * stream reaches this point (fsmmc_job_sync).  Calls no hipMalloc, hipFree,
+ * memset or allocating routine.  Limit: n_points * (dim rounded up to 64, + 1)
+ * * 4 bytes <= FSMMC_NOALLOC_SCRATCH_BYTES (16256 points at dim 100), else
+ * EINVAL.  Every call on one GPU shares the workspace (and uses the job's
+ * request and partial buffers, like fsmmc_eval_potential), so calls that may
+ * overlap on one GPU -- other streams, other threads -- race and must be
+ * ordered by the caller.  Nothing in the workspace needs to start at zero:
+ * each call writes every entry it reads.  Errors: EINVAL, ENOTSUP (not a
+ * NUTS job), EBUSY (job in a batch or server), EDEVICE. */
+fsmmc_status fsmmc_eval_potential_noalloc(fsmmc_job* job, int32_t n_points, const void* theta,
+                                          void* grad, void* U);
+
 /* Per-chain draw counters t_j (host dst, n_chains uint32).  Synchronises. */
 fsmmc_status fsmmc_chain_progress(fsmmc_job* job, uint32_t* dst);
 

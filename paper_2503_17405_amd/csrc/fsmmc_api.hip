@@ -74,6 +74,55 @@ void harvest(fsmmc_job* j)
 
 }  // namespace fsmmc
 
+// Workspace of fsmmc_eval_potential_noalloc: the padded gradients and
+// potentials of one call before they are packed into the caller's buffers.
+// One copy per device, for the life of the process; every call on a device
+// shares it.  Host code never uses this name as an address: the device
+// address comes from hipGetSymbolAddress, once per device (scratch_setup).
+static __device__ __align__(256) unsigned char scratch[FSMMC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// theta (n x D, row-major) into the request buffer (n x Dp), zero padding.
+__global__ void pack_points_kernel(const float* theta, float* thq, int n, int D, int Dp)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)n * Dp) return;
+    const int r = (int)(i / Dp), d = (int)(i % Dp);
+    thq[i] = d < D ? theta[(size_t)r * D + d] : 0.0f;
+}
+
+// The first D of every Dp entries of g (n rows) into out (n x D); u into U.
+__global__ void unpack_potential_kernel(const float* g, const float* u, float* out, float* U, int n, int D, int Dp)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (out && i < (size_t)n * D) {
+        const int r = (int)(i / D), d = (int)(i % D);
+        out[i] = g[(size_t)r * Dp + d];
+    }
+    if (i < (size_t)n) U[i] = u[i];
+}
+}  // namespace
+
+// Device address of `scratch` on `device` (the current device), looked up
+// once per device.
+static fsmmc_status scratch_setup(int device, void** out)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(FSMMC_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        g_scratch_dev[device] = p;
+    }
+    if (out) *out = g_scratch_dev[device];
+    return FSMMC_OK;
+}
+
 static fsmmc_status job_alloc(fsmmc_job* j, size_t bytes, void** p)
 {
     *p = nullptr;
@@ -160,6 +209,8 @@ fsmmc_status fsmmc_ctx_create(int device, size_t hbm_budget_bytes, fsmmc_ctx** o
     HIP_TRY(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(FSMMC_EINVAL, "no such device");
     HIP_TRY(hipSetDevice(device));
+    fsmmc_status ss = scratch_setup(device, nullptr);
+    if (ss != FSMMC_OK) return ss;
     fsmmc_ctx* c = new fsmmc_ctx();
     c->device = device;
     c->budget = hbm_budget_bytes;
@@ -695,6 +746,36 @@ fsmmc_status fsmmc_eval_potential(fsmmc_job* job, int32_t n_points, const void* 
     (void)hipFree(tg);
     if (tu) (void)hipFree(tu);
     if (e != hipSuccess) return hip_fail(e, "fsmmc_eval_potential");
+    return FSMMC_OK;
+}
+
+fsmmc_status fsmmc_eval_potential_noalloc(fsmmc_job* job, int32_t n_points, const void* theta, void* grad, void* U)
+{
+    if (!job || !theta || !U) return fail(FSMMC_EINVAL, "job, theta or U is NULL");
+    if (job->batch) return fail(FSMMC_EBUSY, "job is stepped by a batch or server");
+    JobDev& d = job->d;
+    if (d.kind != FSMMC_NUTS) return fail(FSMMC_ENOTSUP, "only NUTS jobs evaluate a potential");
+    if (n_points < 1 || n_points > d.m) return fail(FSMMC_EINVAL, "n_points must be in [1, n_chains]");
+    // padded gradients, then the potentials at the next 256-byte boundary
+    const size_t gbytes = ((size_t)n_points * d.Dp * 4 + 255) & ~(size_t)255;
+    if (gbytes + (size_t)n_points * 4 > (size_t)FSMMC_NOALLOC_SCRATCH_BYTES)
+        return fail(FSMMC_EINVAL, "n_points x (padded dim + 1) x 4 bytes exceeds the allocation-free workspace "
+                                  "(FSMMC_NOALLOC_SCRATCH_BYTES)");
+    HIP_TRY(hipSetDevice(job->ctx->device));
+    void* base = nullptr;
+    fsmmc_status st = scratch_setup(job->ctx->device, &base);
+    if (st != FSMMC_OK) return st;
+    float* tg = static_cast<float*>(base);
+    float* tu = reinterpret_cast<float*>(static_cast<unsigned char*>(base) + gbytes);
+    const size_t np = (size_t)n_points * d.Dp;
+    hipLaunchKernelGGL(pack_points_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, job->stream,
+                       (const float*)theta, (float*)d.Thq, n_points, d.D, d.Dp);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(nuts_gradient_dense(d, n_points, tg, tu, d.Dp, job->stream));
+    const size_t nu = std::max((size_t)n_points * d.D, (size_t)n_points);
+    hipLaunchKernelGGL(unpack_potential_kernel, dim3((unsigned)((nu + 255) / 256)), dim3(256), 0, job->stream,
+                       (const float*)tg, (const float*)tu, (float*)grad, (float*)U, n_points, d.D, d.Dp);
+    HIP_TRY(hipGetLastError());
     return FSMMC_OK;
 }
 

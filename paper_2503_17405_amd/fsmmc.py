@@ -26,7 +26,7 @@ EXPORTS = [
     "fsmmc_ctx_create", "fsmmc_ctx_destroy", "fsmmc_ctx_bytes_in_use", "fsmmc_init_chains",
     "fsmmc_step_fsm", "fsmmc_step_synchronized", "fsmmc_collect_samples", "fsmmc_collect_counts",
     "fsmmc_chain_progress", "fsmmc_job_stats", "fsmmc_job_sync", "fsmmc_job_free",
-    "fsmmc_last_error", "fsmmc_version", "fsmmc_eval_potential",
+    "fsmmc_last_error", "fsmmc_version", "fsmmc_eval_potential", "fsmmc_eval_potential_noalloc",
     "fsmmc_batch_create", "fsmmc_batch_run", "fsmmc_batch_stats", "fsmmc_batch_free",
     "fsmmc_clock", "fsmmc_server_create", "fsmmc_server_submit", "fsmmc_server_poll",
     "fsmmc_server_wait", "fsmmc_server_stats", "fsmmc_server_destroy",
@@ -120,6 +120,7 @@ def _load():
         "fsmmc_collect_counts": ([p, p], C.c_int),
         "fsmmc_chain_progress": ([p, p], C.c_int),
         "fsmmc_eval_potential": ([p, i32, p, p, p], C.c_int),
+        "fsmmc_eval_potential_noalloc": ([p, i32, p, p, p], C.c_int),
         "fsmmc_job_stats": ([p, p], C.c_int),
         "fsmmc_job_sync": ([p], C.c_int),
         "fsmmc_job_free": ([p], C.c_int),
@@ -221,6 +222,10 @@ def fsmmc_chain_progress(job, dst):
 
 def fsmmc_eval_potential(job, theta, grad, U):
     _check(lib.fsmmc_eval_potential(job, int(theta.shape[0]), _ptr(theta), _ptr(grad), _ptr(U)))
+
+
+def fsmmc_eval_potential_noalloc(job, theta, grad, U):
+    _check(lib.fsmmc_eval_potential_noalloc(job, int(theta.shape[0]), _ptr(theta), _ptr(grad), _ptr(U)))
 
 
 def fsmmc_job_stats(job):
@@ -371,6 +376,11 @@ class Job:
         U = torch.empty(theta.shape[0], dtype=theta.dtype, device=theta.device)
         fsmmc_eval_potential(self.handle, theta, g, U)
         return U, g
+
+    def potential_noalloc(self, theta, g, U):
+        """fsmmc_eval_potential_noalloc into caller-provided g and U (queued on
+        the job's stream; call sync() before reading them)."""
+        fsmmc_eval_potential_noalloc(self.handle, theta.contiguous(), g, U)
 
     def sync(self):
         fsmmc_job_sync(self.handle)
