@@ -610,6 +610,248 @@ static int dr_fsm_step(const orc_target* t, int n_stages, const double* scales, 
 }
 
 /* ------------------------------------------------------------------ */
+/* Symmetric delayed rejection (Mira 2001; Sec. 7.1): up to M tries per
+ * draw, each proposal re-centred on the previous (rejected) one,
+ *   y_0 = x + sigma z_0,  y_s = y_{s-1} + sigma z_s,
+ * accepted with probability
+ *   alpha_s = min(1, max(0, pi(y_s) - pi*_s) / (pi(x) - pi*_s)),
+ *   pi*_s = max_{j<s} pi(y_j)  (pi*_0 = 0: alpha_0 is the Metropolis ratio).
+ * After M rejections x is kept.  Both densities are taken relative to pi(x)
+ * (the ratio is unchanged), so only differences of log densities are
+ * exponentiated.  Reading: sigma is a standard deviation.               */
+
+/* alpha_s from log pi(x), log pi(y_s) and log pi*_s (-inf for s = 0). */
+double orc_drsym_alpha(double lx, double ly, double lstar)
+{
+    double r = exp(ly - lx), rs = exp(lstar - lx);
+    double a = (r - rs) / (1.0 - rs);
+    if (!(a > 0.0)) a = 0.0;
+    if (a > 1.0) a = 1.0;
+    return a;
+}
+
+static void drsym_propose(const orc_target* t, double sigma, uint64_t seed, uint32_t chain,
+                          uint32_t draw, int s, const double* c, double* y)
+{
+    int D = t->dim;
+    orc_normals(seed, chain, draw, ORC_ROLE_PROP, (uint32_t)s, D, y);
+    for (int i = 0; i < D; ++i) y[i] = c[i] + sigma * y[i];
+}
+
+/* One draw.  Returns the number of tries (1..M); x, lx updated on
+ * acceptance.  work: 2*D.                                               */
+int orc_drsym_sample(const orc_target* t, int M, double sigma, uint64_t seed, uint32_t chain,
+                     uint32_t draw, double* x, double* lx, double* work)
+{
+    int D = t->dim;
+    double *c = work, *y = work + D;
+    memcpy(c, x, sizeof(double) * (size_t)D);
+    double lstar = -INFINITY;
+    int s = 0;
+    while (s < M) {
+        drsym_propose(t, sigma, seed, chain, draw, s, c, y);
+        double ly = orc_logpdf(t, y);
+        double a = orc_drsym_alpha(*lx, ly, lstar);
+        double u = orc_uniform(seed, chain, draw, ORC_ROLE_ACC, (uint32_t)s);
+        ++s;
+        if (decide(u < a, u - a, 1.0)) {
+            memcpy(x, y, sizeof(double) * (size_t)D);
+            *lx = ly;
+            break;
+        }
+        if (ly > lstar) lstar = ly;
+        memcpy(c, y, sizeof(double) * (size_t)D);
+    }
+    return s;
+}
+
+/* As an FSM: the loop body (one try) is the single PROPOSE state with INIT
+ * and DONE bundled into it (Sec. 7.1: they are essentially empty).  One
+ * step = one try; returns 1 when the step ends a draw.                    */
+typedef struct {
+    int s;
+    uint32_t t;
+    double lx, lstar;
+    double *x, *c, *y;
+} drsym_fsm;
+
+static int drsym_fsm_step(const orc_target* t, int M, double sigma, uint64_t seed, uint32_t chain,
+                          drsym_fsm* f)
+{
+    int D = t->dim;
+    drsym_propose(t, sigma, seed, chain, f->t, f->s, f->c, f->y);
+    double ly = orc_logpdf(t, f->y);
+    double a = orc_drsym_alpha(f->lx, ly, f->lstar);
+    double u = orc_uniform(seed, chain, f->t, ORC_ROLE_ACC, (uint32_t)f->s);
+    f->s++;
+    int end = 0;
+    if (u < a) {
+        memcpy(f->x, f->y, sizeof(double) * (size_t)D);
+        f->lx = ly;
+        end = 1;
+    } else if (f->s >= M) {
+        end = 1;
+    } else {
+        if (ly > f->lstar) f->lstar = ly;
+        memcpy(f->c, f->y, sizeof(double) * (size_t)D);
+    }
+    if (end) { /* DONE, then INIT of the next draw */
+        memcpy(f->c, f->x, sizeof(double) * (size_t)D);
+        f->lstar = -INFINITY;
+    }
+    return end;
+}
+
+/* ------------------------------------------------------------------ */
+/* Slice sampling along a random direction (Neal 2003: stepping out and
+ * shrinkage, Sec. 4; a random line through x for a multivariate target,
+ * Sec. 5.1).  Sec. 3.1's slice panel: S1 INIT E, S2 EXPAND, S3 INIT S,
+ * S4 SHRINK, S5 DONE.  Draw t from x:
+ *   log y = log pi(x) + ln u;  d = z / |z|;  L = -w u', R = L + w;
+ *   while an end is inside the slice (log pi > log y): step out the left end
+ *   if it is inside, else the right one, by w;
+ *   point x' = x + t d, t uniform on [L, R]; while log pi(x') <= log y:
+ *   shrink the side of t (t < 0: L = t, else R = t) and draw again.
+ * Loop count N = log-density evaluations (2 + steps out + 1 + shrinks).
+ * Guard: a draw stops (x kept) after ORC_ESS_MAX_EVALS evaluations.      */
+
+static double slice_eval(const orc_target* t, const double* x, const double* d, double s, double* xp)
+{
+    for (int i = 0; i < t->dim; ++i) xp[i] = x[i] + s * d[i];
+    return orc_logpdf(t, xp);
+}
+
+static void slice_direction(int D, uint64_t seed, uint32_t chain, uint32_t draw, double* d)
+{
+    orc_normals(seed, chain, draw, ORC_ROLE_NU, 0, D, d);
+    double n = 0.0;
+    for (int i = 0; i < D; ++i) n += d[i] * d[i];
+    n = sqrt(n);
+    for (int i = 0; i < D; ++i) d[i] /= n;
+}
+
+/* Returns N (> 0), or -N when the guard stopped the draw.  work: 3*D.   */
+int orc_slice_sample(const orc_target* t, double w, uint64_t seed, uint32_t chain, uint32_t draw,
+                     double* x, double* lx, double* work)
+{
+    int D = t->dim;
+    double *d = work, *xp = work + D, *xb = work + 2 * D;
+    double logy = *lx + log(orc_uniform(seed, chain, draw, ORC_ROLE_THRESH, 0));
+    slice_direction(D, seed, chain, draw, d);
+    double L = -w * orc_uniform(seed, chain, draw, ORC_ROLE_ANGLE, 0), R = L + w;
+    double lL = slice_eval(t, x, d, L, xp), lR = slice_eval(t, x, d, R, xp);
+    int evals = 2;
+    int inL = decide(lL > logy, lL - logy, 1.0 + fabs(lL) + fabs(logy));
+    int inR = decide(lR > logy, lR - logy, 1.0 + fabs(lR) + fabs(logy));
+    while (inL || inR) {
+        if (evals >= ORC_ESS_MAX_EVALS) return -evals;
+        if (inL) {
+            L -= w;
+            lL = slice_eval(t, x, d, L, xp);
+            inL = decide(lL > logy, lL - logy, 1.0 + fabs(lL) + fabs(logy));
+        } else {
+            R += w;
+            lR = slice_eval(t, x, d, R, xp);
+            inR = decide(lR > logy, lR - logy, 1.0 + fabs(lR) + fabs(logy));
+        }
+        ++evals;
+    }
+    for (int s = 0;; ++s) {
+        if (evals >= ORC_ESS_MAX_EVALS) return -evals;
+        double tt = L + (R - L) * orc_uniform(seed, chain, draw, ORC_ROLE_ANGLE, (uint32_t)(1 + s));
+        double lp = slice_eval(t, x, d, tt, xb);
+        ++evals;
+        if (decide(lp > logy, lp - logy, 1.0 + fabs(lp) + fabs(logy))) {
+            memcpy(x, xb, sizeof(double) * (size_t)D);
+            *lx = lp;
+            return evals;
+        }
+        if (decide(tt < 0.0, tt, fabs(L) + fabs(R)))
+            L = tt;
+        else
+            R = tt;
+    }
+}
+
+/* The same draw as an FSM, one block per step (INIT E, EXPAND, INIT S,
+ * SHRINK, DONE).                                                          */
+enum { SL_INITE = 1, SL_EXPAND = 2, SL_INITS = 3, SL_SHRINK = 4, SL_DONE = 5 };
+
+typedef struct {
+    int k, evals, inL, inR, acc, s, guard;
+    uint32_t t;
+    double lx, logy, L, R, tt, lp;
+    double *x, *d, *xp, *xb;
+} slice_fsm;
+
+static int slice_fsm_step(const orc_target* t, double w, uint64_t seed, uint32_t chain, slice_fsm* f)
+{
+    int D = t->dim;
+    int is_sample = 0;
+    switch (f->k) {
+    case SL_INITE: {
+        f->logy = f->lx + log(orc_uniform(seed, chain, f->t, ORC_ROLE_THRESH, 0));
+        slice_direction(D, seed, chain, f->t, f->d);
+        f->L = -w * orc_uniform(seed, chain, f->t, ORC_ROLE_ANGLE, 0);
+        f->R = f->L + w;
+        f->inL = slice_eval(t, f->x, f->d, f->L, f->xp) > f->logy;
+        f->inR = slice_eval(t, f->x, f->d, f->R, f->xp) > f->logy;
+        f->evals = 2;
+        f->guard = 0;
+        f->k = (f->inL || f->inR) ? SL_EXPAND : SL_INITS;
+        break;
+    }
+    case SL_EXPAND:
+        if (f->evals >= ORC_ESS_MAX_EVALS) {
+            f->guard = 1;
+            f->k = SL_DONE;
+            break;
+        }
+        if (f->inL) {
+            f->L -= w;
+            f->inL = slice_eval(t, f->x, f->d, f->L, f->xp) > f->logy;
+        } else {
+            f->R += w;
+            f->inR = slice_eval(t, f->x, f->d, f->R, f->xp) > f->logy;
+        }
+        f->evals++;
+        f->k = (f->inL || f->inR) ? SL_EXPAND : SL_INITS;
+        break;
+    case SL_INITS:
+    case SL_SHRINK:
+        if (f->k == SL_SHRINK) {
+            if (f->tt < 0.0)
+                f->L = f->tt;
+            else
+                f->R = f->tt;
+            f->s++;
+        } else {
+            f->s = 0;
+        }
+        if (f->evals >= ORC_ESS_MAX_EVALS) {
+            f->guard = 1;
+            f->k = SL_DONE;
+            break;
+        }
+        f->tt = f->L + (f->R - f->L) * orc_uniform(seed, chain, f->t, ORC_ROLE_ANGLE, (uint32_t)(1 + f->s));
+        f->lp = slice_eval(t, f->x, f->d, f->tt, f->xb);
+        f->evals++;
+        f->acc = f->lp > f->logy;
+        f->k = f->acc ? SL_DONE : SL_SHRINK;
+        break;
+    case SL_DONE:
+        if (!f->guard) {
+            memcpy(f->x, f->xb, sizeof(double) * (size_t)D);
+            f->lx = f->lp;
+        }
+        is_sample = 1;
+        f->k = SL_INITE;
+        break;
+    }
+    return is_sample;
+}
+
+/* ------------------------------------------------------------------ */
 /* No-U-Turn sampler (Hoffman & Gelman 2014) in the iterative two-nested-
  * loop form the paper converts (Sec. 7.3: an outer loop that doubles the
  * trajectory, an inner loop that integrates it while watching for U-turns
@@ -960,7 +1202,7 @@ static int nuts_fsm_step(const orc_target* t, double eps, int max_depth, uint64_
 /* ------------------------------------------------------------------ */
 /* Chain runners: Alg. "MCMC algorithm with sample function" (use_fsm = 0)
  * or Alg. "FSM MCMC algorithm" (use_fsm = 1).                          */
-enum { ORC_ESS = 0, ORC_NUTS = 1, ORC_DRMH = 2 };
+enum { ORC_ESS = 0, ORC_NUTS = 1, ORC_DRMH = 2, ORC_DRSYM = 3, ORC_SLICE = 4 };
 
 typedef struct {
     int32_t kind;
@@ -1074,6 +1316,93 @@ int orc_run_chain(const orc_target* t, const orc_sampler* sp, uint64_t seed, uin
             }
         }
         free(buf);
+    } else if (sp->kind == ORC_SLICE) {
+        /* scales[0] = w, the stepping-out width */
+        if (!(sp->scales[0] > 0.0)) return -1;
+        double* buf = (double*)malloc(sizeof(double) * (size_t)D * 4);
+        double *x = buf, *work = buf + D;
+        if (x0)
+            memcpy(x, x0, sizeof(double) * D);
+        else if (t->kind == ORC_FUNNEL)
+            orc_funnel_init(D, seed, chain, x);
+        else
+            orc_normal_init(D, seed, chain, x);
+        double lx = orc_logpdf(t, x);
+        if (!use_fsm) {
+            for (int i = 0; i < n; ++i) {
+                int s = orc_slice_sample(t, sp->scales[0], seed, chain, (uint32_t)i, x, &lx, work);
+                if (s < 0) {
+                    ++guards;
+                    s = -s;
+                }
+                if (counts) counts[i] = s;
+                memcpy(out + (size_t)i * D, x, sizeof(double) * D);
+            }
+        } else {
+            slice_fsm f;
+            memset(&f, 0, sizeof(f));
+            f.k = SL_INITE;
+            f.lx = lx;
+            f.x = x;
+            f.d = work;
+            f.xp = work + D;
+            f.xb = work + 2 * D;
+            while ((int)f.t < n) {
+                int k0 = f.k;
+                int is_sample = slice_fsm_step(t, sp->scales[0], seed, chain, &f);
+                ++nsteps;
+                if (edges) edges[k0 * 6 + f.k]++;
+                if (is_sample) {
+                    if (f.guard) ++guards;
+                    if (counts) counts[f.t] = f.evals;
+                    memcpy(out + (size_t)f.t * D, f.x, sizeof(double) * D);
+                    f.t++;
+                }
+            }
+        }
+        free(buf);
+    } else if (sp->kind == ORC_DRSYM) {
+        /* n_stages = M tries, scales[0] = sigma */
+        if (sp->n_stages < 1) return -1;
+        double* buf = (double*)malloc(sizeof(double) * (size_t)D * 3);
+        double *x = buf, *work = buf + D;
+        if (x0)
+            memcpy(x, x0, sizeof(double) * D);
+        else if (t->kind == ORC_FUNNEL)
+            orc_funnel_init(D, seed, chain, x);
+        else
+            orc_normal_init(D, seed, chain, x);
+        double lx = orc_logpdf(t, x);
+        if (!use_fsm) {
+            for (int i = 0; i < n; ++i) {
+                int s = orc_drsym_sample(t, sp->n_stages, sp->scales[0], seed, chain, (uint32_t)i, x, &lx,
+                                         work);
+                if (counts) counts[i] = s;
+                memcpy(out + (size_t)i * D, x, sizeof(double) * D);
+            }
+        } else {
+            drsym_fsm f;
+            f.s = 0;
+            f.t = 0;
+            f.lx = lx;
+            f.lstar = -INFINITY;
+            f.x = x;
+            f.c = work;
+            f.y = work + D;
+            memcpy(f.c, x, sizeof(double) * D);
+            while ((int)f.t < n) {
+                int is_sample = drsym_fsm_step(t, sp->n_stages, sp->scales[0], seed, chain, &f);
+                ++nsteps;
+                if (edges) edges[2 * 4 + 2]++; /* PROPOSE -> PROPOSE (INIT and DONE bundled) */
+                if (is_sample) {
+                    if (counts) counts[f.t] = f.s;
+                    memcpy(out + (size_t)f.t * D, f.x, sizeof(double) * D);
+                    f.t++;
+                    f.s = 0;
+                }
+            }
+        }
+        free(buf);
     } else if (sp->kind == ORC_NUTS) {
         if (sp->max_depth < 1 || sp->max_depth > ORC_NUTS_MAXJ) return -1;
         double* buf = (double*)malloc(sizeof(double) * ((size_t)D * 2 + nuts_ws_len(D)));
@@ -1148,6 +1477,17 @@ int orc_draw_traced(const orc_target* t, const orc_sampler* sp, uint64_t seed, u
         double* work = (double*)calloc((size_t)D * 3, sizeof(double));
         double lx = orc_logpdf(t, x);
         r = orc_dr_sample(t, sp->n_stages, sp->scales, seed, chain, draw, x, &lx, work);
+        free(work);
+    } else if (sp->kind == ORC_SLICE && sp->scales[0] > 0.0) {
+        double* work = (double*)calloc((size_t)D * 3, sizeof(double));
+        double lx = orc_logpdf(t, x);
+        r = orc_slice_sample(t, sp->scales[0], seed, chain, draw, x, &lx, work);
+        if (r < 0) r = -r;
+        free(work);
+    } else if (sp->kind == ORC_DRSYM && sp->n_stages >= 1) {
+        double* work = (double*)calloc((size_t)D * 2, sizeof(double));
+        double lx = orc_logpdf(t, x);
+        r = orc_drsym_sample(t, sp->n_stages, sp->scales[0], seed, chain, draw, x, &lx, work);
         free(work);
     } else if (sp->kind == ORC_NUTS && sp->max_depth >= 1 && sp->max_depth <= ORC_NUTS_MAXJ) {
         /* zeroed: a replay with an inverted decision may read a slot that the

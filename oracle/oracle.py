@@ -24,7 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 # target kinds
 GP_GAUSS, GP_LOGISTIC, LOGREG, FUNNEL, GAUSS_DIAG, MOG = 0, 1, 2, 3, 4, 5
 # sampler kinds
-ESS, NUTS, DRMH = 0, 1, 2
+ESS, NUTS, DRMH, DRSYM, SLICE = 0, 1, 2, 3, 4
 # stream roles
 ROLE_NU, ROLE_INIT, ROLE_THRESH, ROLE_ANGLE = 1, 2, 3, 4
 ROLE_MOM, ROLE_DIR, ROLE_LEAF, ROLE_MERGE, ROLE_PROP, ROLE_ACC = 5, 6, 7, 8, 9, 10
@@ -86,6 +86,10 @@ def lib():
             L.orc_log1mexp.argtypes = [d]
             L.orc_dr_log_alpha1.restype = d
             L.orc_dr_log_alpha1.argtypes = [d, d]
+            L.orc_drsym_alpha.restype = d
+            L.orc_drsym_alpha.argtypes = [d, d, d]
+            L.orc_drsym_sample.restype = i32
+            L.orc_drsym_sample.argtypes = [p, i32, d, u64, u32, u32, p, p, p]
             L.orc_dr_log_alpha2.restype = d
             L.orc_dr_log_alpha2.argtypes = [d, d, d, d, d]
             L.orc_dr_log_alpha3.restype = d
@@ -190,6 +194,17 @@ def dr_sampler(scales=(1.0, 0.3, 0.1), n_stages=None):
     return Sampler(DRMH, n_stages=n, scales=scales)
 
 
+def slice_sampler(width=1.0):
+    """Slice sampling along a random direction, stepping-out width `width`."""
+    return Sampler(SLICE, scales=(float(width),))
+
+
+def drsym_sampler(n_tries=100, sigma=0.1):
+    """Symmetric delayed rejection: up to n_tries re-centred proposals of
+    standard deviation sigma per draw."""
+    return Sampler(DRSYM, n_stages=int(n_tries), scales=(float(sigma),))
+
+
 # ---------------------------------------------------------------- RNG
 def philox(ctr, key):
     c = np.asarray(ctr, dtype=np.uint32).copy()
@@ -230,6 +245,19 @@ def logpdf(target, x):
 # ---------------------------------------------------------------- pieces
 def log1mexp(a):
     return lib().orc_log1mexp(float(a))
+
+
+def drsym_alpha(lx, ly, lstar):
+    return lib().orc_drsym_alpha(float(lx), float(ly), float(lstar))
+
+
+def drsym_sample(target, n_tries, sigma, seed, chain, draw, x):
+    x = _f64(x).copy()
+    lx = C.c_double(logpdf(target, x))
+    work = np.zeros(2 * target.dim)
+    s = lib().orc_drsym_sample(target.ref, int(n_tries), float(sigma), seed, chain, draw, _ptr(x),
+                               C.byref(lx), _ptr(work))
+    return x, s
 
 
 def dr_log_alpha1(la, lb):
@@ -325,7 +353,7 @@ def run_chain(target, sampler, seed, chain, n, x0=None, use_fsm=False, want_edge
         raise ValueError("oracle rejected the arguments")
     res = dict(draws=out, counts=counts, guards=g, steps=int(steps[0]))
     if want_edges:
-        K = 6 if sampler.kind == NUTS else 4
+        K = 6 if sampler.kind in (NUTS, SLICE) else 4
         res["edges"] = edges[:K * K].reshape(K, K)
     return res
 
