@@ -57,14 +57,23 @@ typedef enum {
     FSMMC_GP_LOGISTIC = 1, /* latent GP, prior N(0, L L^T), y_i ~ Bern(sigmoid f_i)   */
     FSMMC_LOGREG = 2,      /* Bayesian logistic regression, prior N(0, I)            */
     FSMMC_FUNNEL = 3,      /* Neal's funnel: v ~ N(0, 9), x_i | v ~ N(0, e^v)        */
-    FSMMC_GAUSS_DIAG = 4   /* N(0, diag(prec)^-1)                                    */
+    FSMMC_GAUSS_DIAG = 4,  /* N(0, diag(prec)^-1)                                    */
+    FSMMC_MOG = 5          /* mixture of K Gaussians sharing one covariance (Sec. 7.3):
+                              pi(x) ∝ sum_k w_k exp(-(x - mu_k)^T P (x - mu_k) / 2)  */
 } fsmmc_target_kind;
 
 /* Samplers (Sec. 3.1, Fig. "Finite state machines for the sample function"). */
 typedef enum {
     FSMMC_ESS = 0,  /* elliptical slice sampling: INIT, SHRINK, DONE                  */
     FSMMC_NUTS = 1, /* no-U-turn HMC: INIT, DOUBLE, INTEGRATE, CHECK, DONE            */
-    FSMMC_DRMH = 2  /* delayed-rejection MH: INIT, PROPOSE, DONE                      */
+    FSMMC_DRMH = 2, /* delayed-rejection MH: INIT, PROPOSE, DONE                      */
+    FSMMC_DRSYM = 3, /* symmetric delayed rejection (Mira 2001; Sec. 7.1): up to n_stages
+                       tries, each proposal N(previous rejected proposal, scales[0]^2 I),
+                       accepted with probability min(1, max(0, pi(y) - pi*) / (pi(x) - pi*)),
+                       pi* the largest density rejected so far in the draw            */
+    FSMMC_SLICE = 4 /* slice sampling along a random direction (Neal 2003): INIT E,
+                       EXPAND, INIT S, SHRINK, DONE (Sec. 3.1); scales[0] is the
+                       stepping-out width w                                           */
 } fsmmc_sampler_kind;
 
 typedef enum { FSMMC_F32 = 0, FSMMC_F64 = 1 } fsmmc_dtype;
@@ -82,14 +91,16 @@ typedef enum {
 typedef struct {
     int32_t kind;     /* fsmmc_target_kind                                         */
     int32_t dim;      /* d >= 1                                                    */
-    int32_t n_data;   /* LOGREG: number of rows of X                               */
+    int32_t n_data;   /* LOGREG: number of rows of X; MOG: components K in [1, 8]   */
     int32_t reserved; /* must be 0                                                 */
-    const void* X;    /* LOGREG: n_data x dim design matrix                        */
+    const void* X;    /* LOGREG: n_data x dim design matrix; MOG: K x dim means mu_k */
     const void* y;    /* GP: dim observations (GAUSS) or labels in {0,1} (LOGISTIC);
-                         LOGREG: n_data labels in {0,1}                            */
+                         LOGREG: n_data labels in {0,1}; MOG: K log weights log w_k */
     const void* chol_L; /* GP: dim x dim lower Cholesky factor of the prior covariance
                            (entries above the diagonal are ignored)                */
-    const void* prec; /* GAUSS_DIAG: dim precisions                                */
+    const void* prec; /* GAUSS_DIAG: dim precisions; MOG: dim x dim precision
+                         matrix P (symmetric positive definite), shared by all
+                         components                                            */
     double noise_sd;  /* GP_GAUSS: observation noise standard deviation            */
 } fsmmc_target_spec;
 
@@ -98,9 +109,12 @@ typedef struct {
     int32_t kind;      /* fsmmc_sampler_kind                                        */
     int32_t dtype;     /* fsmmc_dtype                                               */
     int32_t max_depth; /* NUTS: maximum tree depth J in [1, 15] (<= 2^J - 1 leapfrogs) */
-    int32_t n_stages;  /* DRMH: number of proposal stages in [1, 3]                 */
+    int32_t n_stages;  /* DRMH: number of proposal stages in [1, 3]; DRSYM: maximum
+                          number of tries M in [1, 2^20]                          */
     double step_size;  /* NUTS: leapfrog step size > 0                              */
-    double scales[4];  /* DRMH: proposal standard deviation of each stage > 0       */
+    double scales[4];  /* DRMH: proposal standard deviation of each stage > 0;
+                          DRSYM: scales[0] is the proposal standard deviation;
+                          SLICE: scales[0] is the stepping-out width > 0         */
 } fsmmc_sampler_spec;
 
 /* Launch tuning (0 = library default).  Tuning never changes the draws. */
@@ -108,8 +122,14 @@ typedef struct {
     int32_t window;        /* ESS: draws of ellipse directions precomputed per chain */
     int32_t timing;        /* 1: time every kernel launch with HIP events on the job's
                               stream (reported by fsmmc_job_stats)                   */
-    int32_t reserved[6];
+    int32_t fsm_states;    /* DRSYM: 0 or 1 = condensed FSM (the loop body is one state,
+                              one try per step); 4 = the loop body split into four
+                              states PROPOSE, EVAL, TEST, NEXT, one per step (Sec.
+                              7.1's ablation of bundling); same draws either way  */
+    int32_t reserved[5];
 } fsmmc_tune;
+
+#define FSMMC_HIST_BINS 1025
 
 typedef struct {
     int64_t steps;        /* FSM steps executed, summed over chains (one step = one
@@ -126,6 +146,28 @@ typedef struct {
      * kernels, [2] synchronized-runtime kernels, [3] padding kernels.        */
     double kernel_ms[4];
     int32_t kernel_launches[4];
+    /* Loop counts N_ij (Sec. 2.2; Sec. 4, R(m)) over the draws produced so far:
+     * hist[b] counts draws with N_ij = b for b < FSMMC_HIST_BINS - 1, the last
+     * bin those with N_ij >= FSMMC_HIST_BINS - 1; mean_loops is the mean of
+     * N_ij; over the draws i every chain has produced, mean_max_loops is the
+     * mean of max_j N_ij and r_hat = mean_max_loops / (the mean of N_ij over
+     * those draws): the measured ratio R(m) that bounds the FSM's gain. */
+    double mean_loops;
+    double mean_max_loops;
+    double r_hat;
+    /* Lane occupancy.  Lane-per-chain kernels (DRMH, alone or in a batch)
+     * count in the kernel: a wave runs its loop body as often as its busiest
+     * lane, so it spends 64 lane slots per iteration, of which the lanes whose
+     * chain still had work are active.  Wave-per-chain kernels (ESS, NUTS)
+     * keep all of a running chain's lanes on its dim coordinates: active =
+     * steps * dim, slots = (steps + padded_steps) * dim rounded up to 64. */
+    int64_t active_lanes;
+    int64_t lane_slots;
+    /* NUTS: sum over every leapfrog so far of min(1, exp(H0 - H)) (a
+     * divergent or undefined energy counts 0); divided by steps it is the
+     * mean acceptance statistic that step-size tuning targets. */
+    double accept_sum;
+    int64_t hist[FSMMC_HIST_BINS];
 } fsmmc_stats;
 
 typedef struct fsmmc_ctx fsmmc_ctx;

@@ -147,11 +147,14 @@ __global__ __launch_bounds__(256) void batch_fsm_kernel(const BJob* jobs_in, con
                 else
                     nd += dr_run<WIDE ? 16 : 12>(a, c, stop, &steps, &live);
             }
-            // one atomic per wave and counter
+            // one atomic per wave and counter; lane occupancy as in dr_count_lanes
             const unsigned long long st = wave_sum_u64(steps), lv = wave_sum_u64(live);
+            const unsigned long long slots = 64ull * (unsigned long long)wave_max_i32((int)steps);
             if (lane == 0) {
                 if (st) atomicAdd(&a.ctr[0], st);
                 if (lv) atomicAdd(&a.ctr[4], lv);
+                if (st) atomicAdd(&a.ctr[5], st);
+                if (slots) atomicAdd(&a.ctr[6], slots);
             }
         }
     }
@@ -528,6 +531,10 @@ fsmmc_status batch_admissible(const fsmmc_batch* b, const fsmmc_job* j)
     if (j->ctx != b->ctx) return fail(FSMMC_EINVAL, "job belongs to another context");
     if (j->batch) return fail(FSMMC_EBUSY, "job is already in a batch");
     if (j->d.dtype != FSMMC_F32) return fail(FSMMC_ENOTSUP, "batches run FP32 jobs");
+    if (j->d.kind == FSMMC_NUTS && j->d.target != FSMMC_LOGREG)
+        return fail(FSMMC_ENOTSUP, "batches run NUTS on LOGREG targets only");
+    if (j->d.kind == FSMMC_DRSYM || j->d.kind == FSMMC_SLICE)
+        return fail(FSMMC_ENOTSUP, "batches do not run DRSYM or SLICE jobs");
     return FSMMC_OK;
 }
 

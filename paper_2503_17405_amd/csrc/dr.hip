@@ -32,6 +32,7 @@ __global__ __launch_bounds__(256) void dr_fsm_kernel(DrK a)
     if (threadIdx.x == 0 && st) atomicAdd(&a.ctr[0], st);
     const unsigned long long lv = block_sum_u64(wave_sum_u64(live), &s_sum);
     if (threadIdx.x == 0 && lv) atomicAdd(&a.ctr[4], lv);
+    dr_count_lanes(a, steps, steps, &s_sum);
 }
 
 template <int NM>
@@ -63,6 +64,7 @@ __global__ __launch_bounds__(256) void dr_sync_kernel(DrK a, uint32_t draw)
     if (threadIdx.x == 0) atomicMax(&a.maxN[draw], mx);
     const unsigned long long st = block_sum_u64(wave_sum_u64((unsigned long long)steps), &s_sum);
     if (threadIdx.x == 0 && st) atomicAdd(&a.ctr[0], st);
+    dr_count_lanes(a, (uint32_t)steps, (uint32_t)steps, &s_sum);
 }
 
 // The stage bodies a batched while loop runs after chain c has finished
@@ -96,6 +98,7 @@ __global__ __launch_bounds__(256) void dr_pad_kernel(DrK a, uint32_t draw)
     if (c < a.m) extra = dr_pad_one<NM>(a, c, draw);
     const unsigned long long tot = block_sum_u64(wave_sum_u64((unsigned long long)extra), &s_sum);
     if (threadIdx.x == 0 && tot) atomicAdd(&a.ctr[1], tot);
+    dr_count_lanes(a, 0u, (uint32_t)extra, &s_sum);  // discarded bodies: slots, no useful lanes
 }
 
 // Default starts: an exact funnel draw (v = 3 z0, x_i = e^{v/2} z_i) or N(0, I).

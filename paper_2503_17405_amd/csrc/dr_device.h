@@ -235,6 +235,20 @@ __device__ __forceinline__ uint32_t dr_run(const DrK& a, int c, uint32_t stop, u
     return L.t - t0;
 }
 
+// Lane occupancy of a lane-per-chain loop (every thread of the block calls
+// it): a wave runs its loop body as often as its busiest lane, so it spends
+// 64 * max(iters) lane slots, of which sum(useful) did a chain's work.
+// ctr[5] += useful lane-iterations, ctr[6] += lane slots; one atomic per block.
+__device__ __forceinline__ void dr_count_lanes(const DrK& a, uint32_t useful, uint32_t iters,
+                                               unsigned long long* s_slot)
+{
+    const unsigned long long act = block_sum_u64(wave_sum_u64((unsigned long long)useful), s_slot);
+    if (threadIdx.x == 0 && act) atomicAdd(&a.ctr[5], act);
+    const unsigned long long slots =
+        block_sum_u64(64ull * (unsigned long long)wave_max_i32((int)iters), s_slot);
+    if (threadIdx.x == 0 && slots) atomicAdd(&a.ctr[6], slots);
+}
+
 inline DrK dr_view(const JobDev& j)
 {
     DrK a;

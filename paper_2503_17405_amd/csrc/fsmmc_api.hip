@@ -251,14 +251,43 @@ fsmmc_status fsmmc::validate_specs(const fsmmc_target_spec* t, const fsmmc_sampl
         return FSMMC_OK;
     }
     if (s->kind == FSMMC_NUTS) {
-        if (t->kind != FSMMC_LOGREG) return fail(FSMMC_ENOTSUP, "NUTS is built for LOGREG targets");
+        if (t->kind != FSMMC_LOGREG && t->kind != FSMMC_MOG)
+            return fail(FSMMC_ENOTSUP, "NUTS is built for LOGREG and MOG targets");
         if (s->dtype != FSMMC_F32) return fail(FSMMC_ENOTSUP, "NUTS is built for FP32");
-        if (!t->X || !t->y) return fail(FSMMC_EINVAL, "LOGREG target needs X and y");
-        if (t->n_data < 1) return fail(FSMMC_EINVAL, "n_data must be >= 1");
+        if (t->kind == FSMMC_LOGREG) {
+            if (!t->X || !t->y) return fail(FSMMC_EINVAL, "LOGREG target needs X and y");
+            if (t->n_data < 1) return fail(FSMMC_EINVAL, "n_data must be >= 1");
+        } else {
+            if (!t->X || !t->y || !t->prec) return fail(FSMMC_EINVAL, "MOG target needs means, log weights and prec");
+            if (t->n_data < 1 || t->n_data > 8) return fail(FSMMC_EINVAL, "MOG needs 1 to 8 components");
+        }
         if (t->dim > 128) return fail(FSMMC_ENOTSUP, "NUTS dim must be <= 128");
         if (s->max_depth < 1 || s->max_depth > 15) return fail(FSMMC_EINVAL, "max_depth must be in [1, 15]");
         if (!(s->step_size > 0.0) || !std::isfinite(s->step_size))
             return fail(FSMMC_EINVAL, "step_size must be > 0");
+        return FSMMC_OK;
+    }
+    if (s->kind == FSMMC_SLICE) {
+        if (t->kind != FSMMC_FUNNEL && t->kind != FSMMC_GAUSS_DIAG)
+            return fail(FSMMC_ENOTSUP, "SLICE is built for FUNNEL and GAUSS_DIAG targets");
+        if (s->dtype != FSMMC_F32) return fail(FSMMC_ENOTSUP, "SLICE is built for FP32");
+        if (t->dim > dr_max_dim()) return fail(FSMMC_ENOTSUP, "SLICE dim must be <= 16");
+        if (t->kind == FSMMC_FUNNEL && t->dim < 2) return fail(FSMMC_EINVAL, "FUNNEL needs dim >= 2");
+        if (t->kind == FSMMC_GAUSS_DIAG && !t->prec) return fail(FSMMC_EINVAL, "GAUSS_DIAG needs prec");
+        if (!(s->scales[0] > 0.0) || !std::isfinite(s->scales[0]))
+            return fail(FSMMC_EINVAL, "stepping-out width must be > 0");
+        return FSMMC_OK;
+    }
+    if (s->kind == FSMMC_DRSYM) {
+        if (t->kind != FSMMC_FUNNEL && t->kind != FSMMC_GAUSS_DIAG)
+            return fail(FSMMC_ENOTSUP, "DRSYM is built for FUNNEL and GAUSS_DIAG targets");
+        if (s->dtype != FSMMC_F32) return fail(FSMMC_ENOTSUP, "DRSYM is built for FP32");
+        if (t->dim > dr_max_dim()) return fail(FSMMC_ENOTSUP, "DRSYM dim must be <= 16");
+        if (t->kind == FSMMC_FUNNEL && t->dim < 2) return fail(FSMMC_EINVAL, "FUNNEL needs dim >= 2");
+        if (t->kind == FSMMC_GAUSS_DIAG && !t->prec) return fail(FSMMC_EINVAL, "GAUSS_DIAG needs prec");
+        if (s->n_stages < 1 || s->n_stages > (1 << 20)) return fail(FSMMC_EINVAL, "n_stages (tries) must be in [1, 2^20]");
+        if (!(s->scales[0] > 0.0) || !std::isfinite(s->scales[0]))
+            return fail(FSMMC_EINVAL, "proposal scale must be > 0");
         return FSMMC_OK;
     }
     if (s->kind == FSMMC_DRMH) {
@@ -417,6 +446,47 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
                                          hipMemcpyDeviceToDevice, job->stream));
         HIP_TRY_JOB(ess_prior_draw(d, x0, job->stream));
         job->launches += x0 ? 2 : 3;
+    } else if (d.kind == FSMMC_SLICE) {  // lane per chain, [d][chain] state
+        d.Dp = d.D;
+        ALLOC(d.x, m * (size_t)d.D * 4);
+        ALLOC(d.V, 2 * m * (size_t)d.D * 4);
+        ALLOC(d.logu, m * 4);
+        ALLOC(d.tmin, m * 4);
+        ALLOC(d.tmax, m * 4);
+        ALLOC(d.theta, m * 4);
+        ALLOC(d.Wsum, m * 4);
+        ALLOC(d.flags, m * 4);
+        ALLOC(d.nn, m * 4);
+        ALLOC(d.jd, m * 4);
+        ALLOC(d.vdir, m * 4);
+        ALLOC(d.maxN, 2 * (size_t)d.n * 4);
+        ALLOC(d.sink, m * 4);
+        ALLOC(d.prec, (size_t)d.D * 4);
+        if (target->kind == FSMMC_GAUSS_DIAG)
+            HIP_TRY_JOB(hipMemcpyAsync(d.prec, target->prec, (size_t)d.D * 4, hipMemcpyDeviceToDevice, job->stream));
+        hipLaunchKernelGGL(fill_i32_kernel, dim3((d.m + 255) / 256), dim3(256), 0, job->stream, d.k, 1, d.m);
+        HIP_TRY_JOB(hipGetLastError());
+        HIP_TRY_JOB(sl_init_state(d, x0, job->stream));
+        job->launches += x0 ? 3 : 2;
+    } else if (d.kind == FSMMC_DRSYM) {  // lane per chain, [d][chain] state
+        if (tune && tune->fsm_states != 0 && tune->fsm_states != 1 && tune->fsm_states != 4) {
+            job_release(job);
+            return fail(FSMMC_EINVAL, "fsm_states must be 0, 1 or 4");
+        }
+        d.fsm_states = tune && tune->fsm_states == 4 ? 4 : 1;
+        d.Dp = d.D;
+        ALLOC(d.x, m * (size_t)d.D * 4);
+        ALLOC(d.V, 2 * m * (size_t)d.D * 4);
+        ALLOC(d.H0, m * 4);
+        ALLOC(d.Wsum, m * 4);
+        ALLOC(d.flags, m * 4);
+        ALLOC(d.maxN, (size_t)d.n * 4);
+        ALLOC(d.sink, m * 4);
+        ALLOC(d.prec, (size_t)d.D * 4);
+        if (target->kind == FSMMC_GAUSS_DIAG)
+            HIP_TRY_JOB(hipMemcpyAsync(d.prec, target->prec, (size_t)d.D * 4, hipMemcpyDeviceToDevice, job->stream));
+        HIP_TRY_JOB(drs_init_state(d, x0, job->stream));
+        job->launches += x0 ? 3 : 2;
     } else if (d.kind == FSMMC_DRMH) {  // lane per chain, [d][chain] state
         d.Dp = d.D;
         ALLOC(d.x, m * (size_t)d.D * 4);
@@ -432,6 +502,42 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
         HIP_TRY_JOB(hipGetLastError());
         HIP_TRY_JOB(dr_init_state(d, x0, job->stream));
         job->launches += x0 ? 3 : 2;
+    } else if (target->kind == FSMMC_MOG) {  // NUTS on a mixture: persistent kernel, inline gradient
+        d.EPL = d.D <= 64 ? 1 : 2;
+        d.Dp = 64 * d.EPL;
+        const size_t Dp = (size_t)d.Dp;
+        d.K = target->n_data;
+        d.nvec = nuts_nvec(d.max_depth);
+        ALLOC(d.jd, m * 4);
+        ALLOC(d.vdir, m * 4);
+        ALLOC(d.nn, m * 4);
+        ALLOC(d.flags, m * 4);
+        ALLOC(d.H0, m * 4);
+        ALLOC(d.Wsum, m * 4);
+        ALLOC(d.Wsub, m * 4);
+        ALLOC(d.US, m * 4);
+        ALLOC(d.acc, m * 4);
+        ALLOC(d.V, m * (size_t)d.nvec * Dp * 4);
+        ALLOC(d.Thq, m * Dp * 4);
+        ALLOC(d.req, m * 4);
+        ALLOC(d.wctr, 64);
+        ALLOC(d.queue, 64);
+        ALLOC(d.maxN, (size_t)d.n * 4);
+        ALLOC(d.sink, m * 4);
+        ALLOC(d.prec, Dp * Dp * 4);
+        ALLOC(d.X, (size_t)d.K * d.D * 4);
+        ALLOC(d.y, (size_t)d.K * 4);
+        ALLOC(d.mogB, (size_t)d.K * Dp * 8);
+        ALLOC(d.mogC, (size_t)d.K * 8);
+        HIP_TRY_JOB(hipMemcpy2DAsync(d.prec, Dp * 4, target->prec, (size_t)d.D * 4, (size_t)d.D * 4, (size_t)d.D,
+                                     hipMemcpyDeviceToDevice, job->stream));
+        HIP_TRY_JOB(hipMemcpyAsync(d.X, target->X, (size_t)d.K * d.D * 4, hipMemcpyDeviceToDevice, job->stream));
+        HIP_TRY_JOB(hipMemcpyAsync(d.y, target->y, (size_t)d.K * 4, hipMemcpyDeviceToDevice, job->stream));
+        HIP_TRY_JOB(mog_setup(d, job->stream));
+        hipLaunchKernelGGL(fill_i32_kernel, dim3((d.m + 255) / 256), dim3(256), 0, job->stream, d.k, 1, d.m);
+        HIP_TRY_JOB(hipGetLastError());
+        HIP_TRY_JOB(mog_init_state(d, x0, job->stream));
+        job->launches += x0 ? 3 : 4;
     } else {  // NUTS on logistic regression
         d.EPL = d.D <= 64 ? 1 : 2;
         d.Dp = 64 * d.EPL;
@@ -458,6 +564,7 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
         ALLOC(d.Wsum, m * 4);
         ALLOC(d.Wsub, m * 4);
         ALLOC(d.US, m * 4);
+        ALLOC(d.acc, m * 4);
         ALLOC(d.V, m * (size_t)d.nvec * Dp * 4);
         ALLOC(d.Thq, m * Dp * 4);
         ALLOC(d.req, m * 4);
@@ -546,6 +653,49 @@ static fsmmc_status nuts_run(fsmmc_job* job, int mode, int64_t max_steps, uint32
     return FSMMC_OK;
 }
 
+// NUTS on a mixture.  FSM: one launch of the persistent kernel; every chain
+// runs to tstop or through max_steps gradient evaluations.  Synchronized:
+// one launch per draw (and in vmap mode one padding launch per draw).
+static fsmmc_status mog_fsm(fsmmc_job* job, int64_t max_steps, int32_t* all_done)
+{
+    JobDev& d = job->d;
+    d.tstop = (uint32_t)d.n;
+    const int64_t b = max_steps > 0 ? max_steps : INT64_MAX;
+    HIP_TRY(fill_i64(d.budget, b, d.m, job->stream));
+    job->launches++;
+    HIP_TRY(launch(job, KC_FSM, [&] { return mog_run(d, 0, 0, &job->qticket, job->stream); }));
+    std::vector<uint32_t> t;
+    fsmmc_status s = progress(job, t, nullptr);
+    if (s != FSMMC_OK) return s;
+    harvest(job);
+    if (all_done) {
+        int done = 1;
+        for (uint32_t v : t) done &= v >= (uint32_t)d.n;
+        *all_done = done;
+    }
+    return FSMMC_OK;
+}
+
+static fsmmc_status mog_sync(fsmmc_job* job, int mode, uint32_t t0, uint32_t t1, int32_t* all_done)
+{
+    JobDev& d = job->d;
+    HIP_TRY(fill_i64(d.budget, INT64_MAX, d.m, job->stream));
+    job->launches++;
+    for (uint32_t dr = t0; dr < t1; ++dr) {
+        HIP_TRY(launch(job, KC_SYNC, [&] { return mog_run(d, 1, dr, &job->qticket, job->stream); }));
+        if (mode == FSMMC_SYNC_VMAP)
+            HIP_TRY(launch(job, KC_PAD, [&] { return mog_pad(d, dr, &job->qticket, job->stream); }));
+    }
+    std::vector<uint32_t> t;
+    fsmmc_status s = progress(job, t, nullptr);
+    if (s != FSMMC_OK) return s;
+    harvest(job);
+    for (uint32_t v : t)
+        if (v != t1) return fail(FSMMC_EDEVICE, "synchronized NUTS: a chain did not complete its draw");
+    if (all_done) *all_done = t1 >= (uint32_t)d.n ? 1 : 0;
+    return FSMMC_OK;
+}
+
 // ESS windows [t0 + kW, t0 + (k+1)W): while window k is stepped on the job's
 // stream, the ellipse GEMM of window k+1 runs on the side stream from a
 // snapshot of the draw counters taken at the start of window k (every chain
@@ -593,7 +743,22 @@ fsmmc_status fsmmc_step_fsm(fsmmc_job* job, int64_t max_steps, int32_t* all_done
     if (job->batch) return fail(FSMMC_EBUSY, "job is stepped by a batch or server");
     JobDev& d = job->d;
     HIP_TRY(hipSetDevice(job->ctx->device));
+    if (d.kind == FSMMC_NUTS && d.target == FSMMC_MOG) return mog_fsm(job, max_steps, all_done);
     if (d.kind == FSMMC_NUTS) return nuts_run(job, 0, max_steps, (uint32_t)d.n, all_done);
+    if (d.kind == FSMMC_DRSYM || d.kind == FSMMC_SLICE) {
+        d.tstop = (uint32_t)d.n;
+        const int64_t b = max_steps > 0 ? max_steps : INT64_MAX;
+        HIP_TRY(fill_i64(d.budget, b, d.m, job->stream));
+        job->launches++;
+        HIP_TRY(hipMemsetAsync(d.ctr + 3, 0, 2 * sizeof(unsigned long long), job->stream));
+        HIP_TRY(launch(job, KC_FSM, [&] {
+            return d.kind == FSMMC_SLICE ? sl_fsm_round(d, job->stream) : drs_fsm_round(d, job->stream);
+        }));
+        fsmmc_status s = read_ctr(job);
+        if (s != FSMMC_OK) return s;
+        if (all_done) *all_done = job->h_ctr[4] == 0 ? 1 : 0;
+        return FSMMC_OK;
+    }
     if (d.kind == FSMMC_DRMH) {
         // one persistent launch: every lane runs its chain to n draws or to its budget
         d.tstop = (uint32_t)d.n;
@@ -657,6 +822,11 @@ fsmmc_status fsmmc_step_synchronized(fsmmc_job* job, int32_t n_draws, int32_t mo
         HIP_TRY(hipMemcpy(k.data(), d.evals, k.size() * 4, hipMemcpyDeviceToHost));
         for (int32_t& v : k) v = v == 0 ? 1 : 0;
     }
+    if (d.kind == FSMMC_DRSYM) {  // no try made and no split sub-state pending
+        std::vector<int32_t> e(k.size());
+        HIP_TRY(hipMemcpy(e.data(), d.evals, e.size() * 4, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < k.size(); ++i) k[i] = (e[i] == 0 && k[i] == 0) ? 1 : 0;
+    }
     const uint32_t t0 = t[0];
     for (int i = 0; i < d.m; ++i)
         if (t[i] != t0 || k[i] != 1)
@@ -667,7 +837,24 @@ fsmmc_status fsmmc_step_synchronized(fsmmc_job* job, int32_t n_draws, int32_t mo
             if (all_done) *all_done = t1 >= (uint32_t)d.n ? 1 : 0;
             return FSMMC_OK;
         }
+        if (d.target == FSMMC_MOG) return mog_sync(job, mode, t0, t1, all_done);
         return nuts_run(job, mode == FSMMC_SYNC_VMAP ? 1 : 2, 0, t1, all_done);
+    }
+    if (d.kind == FSMMC_DRSYM || d.kind == FSMMC_SLICE) {
+        const bool sl = d.kind == FSMMC_SLICE;
+        for (uint32_t dr = t0; dr < t1; ++dr) {
+            HIP_TRY(launch(job, KC_SYNC, [&] {
+                return sl ? sl_sync_draw(d, dr, job->stream) : drs_sync_draw(d, dr, job->stream);
+            }));
+            if (mode == FSMMC_SYNC_VMAP)
+                HIP_TRY(launch(job, KC_PAD, [&] {
+                    return sl ? sl_pad_draw(d, dr, job->stream) : drs_pad_draw(d, dr, job->stream);
+                }));
+        }
+        HIP_TRY(hipStreamSynchronize(job->stream));
+        harvest(job);
+        if (all_done) *all_done = t1 >= (uint32_t)d.n ? 1 : 0;
+        return FSMMC_OK;
     }
     if (d.kind == FSMMC_DRMH) {
         for (uint32_t dr = t0; dr < t1; ++dr) {
@@ -727,6 +914,11 @@ fsmmc_status fsmmc_eval_potential(fsmmc_job* job, int32_t n_points, const void* 
     if (d.kind != FSMMC_NUTS) return fail(FSMMC_ENOTSUP, "only NUTS jobs evaluate a potential");
     if (n_points < 1 || n_points > d.m) return fail(FSMMC_EINVAL, "n_points must be in [1, n_chains]");
     HIP_TRY(hipSetDevice(job->ctx->device));
+    if (d.target == FSMMC_MOG) {
+        HIP_TRY(mog_eval(d, n_points, (const float*)theta, (float*)grad, (float*)U, job->stream));
+        HIP_TRY(hipStreamSynchronize(job->stream));
+        return FSMMC_OK;
+    }
     // The positions go through the request buffer, which only the gradient
     // kernels read; results land in temporary buffers so the gradients of
     // chains with a leapfrog in flight are kept.
@@ -756,6 +948,11 @@ fsmmc_status fsmmc_eval_potential_noalloc(fsmmc_job* job, int32_t n_points, cons
     JobDev& d = job->d;
     if (d.kind != FSMMC_NUTS) return fail(FSMMC_ENOTSUP, "only NUTS jobs evaluate a potential");
     if (n_points < 1 || n_points > d.m) return fail(FSMMC_EINVAL, "n_points must be in [1, n_chains]");
+    if (d.target == FSMMC_MOG) {  // no workspace: the evaluation kernel writes the outputs directly
+        HIP_TRY(hipSetDevice(job->ctx->device));
+        HIP_TRY(mog_eval(d, n_points, (const float*)theta, (float*)grad, (float*)U, job->stream));
+        return FSMMC_OK;
+    }
     // padded gradients, then the potentials at the next 256-byte boundary
     const size_t gbytes = ((size_t)n_points * d.Dp * 4 + 255) & ~(size_t)255;
     if (gbytes + (size_t)n_points * 4 > (size_t)FSMMC_NOALLOC_SCRATCH_BYTES)
@@ -809,6 +1006,53 @@ fsmmc_status fsmmc_job_stats(fsmmc_job* job, fsmmc_stats* out)
     for (int c = 0; c < 4; ++c) {
         out->kernel_ms[c] = job->kms[c];
         out->kernel_launches[c] = job->klaunch[c];
+    }
+    const JobDev& d = job->d;
+    // loop counts of the produced draws: histogram, mean, per-draw max over chains
+    std::vector<int32_t> cnt((size_t)d.m * d.n);
+    HIP_TRY(hipMemcpy(cnt.data(), d.counts, cnt.size() * 4, hipMemcpyDeviceToHost));
+    uint32_t tmin = UINT32_MAX;
+    double sum = 0.0;
+    int64_t nd = 0;
+    for (int c = 0; c < d.m; ++c) {
+        tmin = std::min(tmin, t[c]);
+        const int32_t* row = &cnt[(size_t)c * d.n];
+        for (uint32_t i = 0; i < t[c] && i < (uint32_t)d.n; ++i) {
+            const int32_t v = std::max(row[i], 0);
+            out->hist[std::min(v, FSMMC_HIST_BINS - 1)]++;
+            sum += v;
+            ++nd;
+        }
+    }
+    out->mean_loops = nd ? sum / (double)nd : 0.0;
+    if (tmin != UINT32_MAX && tmin > 0) {
+        double smax = 0.0, sall = 0.0;
+        for (uint32_t i = 0; i < tmin; ++i) {
+            int32_t mx = 0;
+            for (int c = 0; c < d.m; ++c) {
+                const int32_t v = std::max(cnt[(size_t)c * d.n + i], 0);
+                mx = std::max(mx, v);
+                sall += v;
+            }
+            smax += mx;
+        }
+        out->mean_max_loops = smax / (double)tmin;
+        const double mean_common = sall / ((double)tmin * (double)d.m);
+        out->r_hat = mean_common > 0.0 ? out->mean_max_loops / mean_common : 0.0;
+    }
+    if (d.kind == FSMMC_DRMH || d.kind == FSMMC_DRSYM || d.kind == FSMMC_SLICE) {
+        out->active_lanes = (int64_t)job->h_ctr[5];
+        out->lane_slots = (int64_t)job->h_ctr[6];
+    } else {
+        out->active_lanes = out->steps * (int64_t)d.D;
+        out->lane_slots = (out->steps + out->padded_steps) * (int64_t)d.Dp;
+    }
+    if (d.kind == FSMMC_NUTS && d.acc) {
+        std::vector<float> acc((size_t)d.m);
+        HIP_TRY(hipMemcpy(acc.data(), d.acc, acc.size() * 4, hipMemcpyDeviceToHost));
+        double a = 0.0;
+        for (float v : acc) a += (double)v;
+        out->accept_sum = a;
     }
     return FSMMC_OK;
 }

@@ -26,6 +26,7 @@ struct JobDev {
     double noise_sd = 0;
     double step_size = 0;
     int max_depth = 0, n_stages = 0;
+    int fsm_states = 1;  // DRSYM: 1 condensed, 4 split loop body
     double scales[4] = {0, 0, 0, 0};
 
     // target data (owned copies)
@@ -74,6 +75,13 @@ struct JobDev {
     uint32_t* wctr = nullptr;  // [0..2] chains still in their draw, [3..5] chains alive (per step mod 3)
     int slice_rows = 0, nslices = 0;
     uint32_t tstop = 0;        // chains stop at this draw count
+    void* acc = nullptr;       // m: sum over leapfrogs of min(1, e^(H0 - H)) (FP32)
+    // NUTS on a Gaussian mixture (gradient computed inline by each chain's wave)
+    int K = 0;                 // components
+    void* mogB = nullptr;      // K x Dp: P mu_k (FP64)
+    void* mogC = nullptr;      // K: log w_k - mu_k^T P mu_k / 2 (FP64)
+    int32_t* queue = nullptr;  // 64 bytes: ticket counter of the persistent kernel
+    int pwpb = 0, pblocks = 0; // its launch shape (waves per block, blocks)
 
     // outputs
     void* out = nullptr;  // m x n x D
@@ -103,6 +111,31 @@ hipError_t nuts_init_state(const JobDev& j, const void* x0, hipStream_t s);
 hipError_t nuts_transition(const JobDev& j, int mode, uint32_t step, hipStream_t s);
 hipError_t nuts_gradient(const JobDev& j, hipStream_t s);
 hipError_t nuts_gradient_dense(const JobDev& j, int ncols, float* Gout, float* Uout, int gstride, hipStream_t s);
+
+// NUTS on a Gaussian mixture (mog.hip): P (Dp x Dp) in d.prec, means in d.X
+// Setup: P mu_k, the constants, and the persistent launch shape (pwpb, pblocks).
+hipError_t mog_setup(JobDev& j, hipStream_t s);
+hipError_t mog_init_state(const JobDev& j, const void* x0, hipStream_t s);
+// sync == 0: FSM, each chain runs to tstop or through its budget; sync != 0:
+// the chains' draw `draw` only (tstop = draw + 1), recording the draw's
+// largest leapfrog count.  ticket: the chain queue's base, advanced here.
+hipError_t mog_run(const JobDev& j, int sync, uint32_t draw, unsigned long long* ticket, hipStream_t s);
+// vmap padding of draw `draw` (after mog_run of that draw).
+hipError_t mog_pad(const JobDev& j, uint32_t draw, unsigned long long* ticket, hipStream_t s);
+// U and grad U at n points (n x D, row-major) into G (n x D, or NULL) and U (n).
+hipError_t mog_eval(const JobDev& j, int n, const float* pts, float* G, float* U, hipStream_t s);
+
+// Slice sampler launchers (slice.hip)
+hipError_t sl_init_state(const JobDev& j, const void* x0, hipStream_t s);
+hipError_t sl_fsm_round(const JobDev& j, hipStream_t s);
+hipError_t sl_sync_draw(const JobDev& j, uint32_t draw, hipStream_t s);
+hipError_t sl_pad_draw(const JobDev& j, uint32_t draw, hipStream_t s);
+
+// Symmetric DR launchers (drsym.hip)
+hipError_t drs_init_state(const JobDev& j, const void* x0, hipStream_t s);
+hipError_t drs_fsm_round(const JobDev& j, hipStream_t s);
+hipError_t drs_sync_draw(const JobDev& j, uint32_t draw, hipStream_t s);
+hipError_t drs_pad_draw(const JobDev& j, uint32_t draw, hipStream_t s);
 
 // DR launchers (dr.hip)
 int dr_max_dim();

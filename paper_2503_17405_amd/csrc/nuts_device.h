@@ -41,34 +41,114 @@ struct NutsK {
     int32_t* counts;
     unsigned long long* ctr;
     uint32_t* wctr;
+    float* acc;       // per chain: sum over its leapfrogs of min(1, e^(H0 - H))
+    int32_t* maxN;    // per draw: largest leapfrog count over chains (synchronized inline runtime)
+    int32_t* queue;   // persistent inline kernel: next chain to take
 };
 
 enum { V_THL = 0, V_PL, V_GL, V_THR, V_PR, V_GR, V_THP, V_GP, V_THS, V_GS, V_RHO, V_RHOS, V_PH, V_FIXED };
 
-// One runtime step of chain c (one wavefront): finish the leapfrog whose
+// One runtime step of a chain (one wavefront): finish the leapfrog whose
 // gradient has arrived, then run the cheap states back to back until the
 // chain requests its next gradient (Appendix, Alg. "bundled step as input to
 // amortized step").
-// Returns NC_ALIVE if the chain is short of tstop afterwards, plus NC_INDRAW
-// if it is also still inside its draw (synchronized runtimes).  Gradient
-// requests (the steps) are counted by the compaction.
-enum NutsChainBits { NC_ALIVE = 1, NC_INDRAW = 2 };
+// NC_REQ: the step ended with a gradient request (the leapfrog is pending).
+enum NutsChainBits { NC_ALIVE = 1, NC_INDRAW = 2, NC_REQ = 4 };
 
-template <int EPL>
-__device__ __forceinline__ int nuts_chain_step(const NutsK& a, int c, int lane)
+// Scalar state of one chain, wave-uniform, held in registers while the
+// chain is stepped.
+struct NutsScal {
+    uint32_t t;
+    int k, j, v, nn, fl, nleap;
+    int64_t budget;
+    float H0, W, Ws, UP, US, acc;
+};
+
+__device__ __forceinline__ NutsScal nuts_load(const NutsK& a, int c, uint32_t t)
 {
-    c = uni(c);
-    uint32_t t = uni(a.t[c]);
-    if (t >= a.tstop) {
-        if (lane == 0) a.req[c] = 0;
-        return 0;
+    NutsScal s;
+    s.t = t;
+    s.k = uni(a.k[c]);
+    s.j = uni(a.jd[c]);
+    s.v = uni(a.v[c]);
+    s.nn = uni(a.nn[c]);
+    s.fl = uni(a.flags[c]);
+    s.nleap = uni(a.nleap[c]);
+    s.budget = uni((int64_t)a.budget[c]);
+    s.H0 = uni(a.H0[c]);
+    s.W = uni(a.W[c]);
+    s.Ws = uni(a.Ws[c]);
+    s.UP = uni(a.UP[c]);
+    s.US = uni(a.US[c]);
+    s.acc = uni(a.acc[c]);
+    return s;
+}
+
+__device__ __forceinline__ void nuts_store(const NutsK& a, int c, const NutsScal& s, int req, int lane)
+{
+    if (lane == 0) {
+        a.t[c] = s.t;
+        a.k[c] = s.k;
+        a.jd[c] = s.j;
+        a.v[c] = s.v;
+        a.nn[c] = s.nn;
+        a.flags[c] = s.fl;
+        a.nleap[c] = s.nleap;
+        a.budget[c] = s.budget;
+        a.H0[c] = s.H0;
+        a.W[c] = s.W;
+        a.Ws[c] = s.Ws;
+        a.UP[c] = s.UP;
+        a.US[c] = s.US;
+        a.acc[c] = s.acc;
+        a.req[c] = req;
     }
+}
+
+// Logistic regression: the gradient of the pending leapfrog arrives as
+// row-slice partials, added in slice order:
+//   grad U = theta - sum_s X_s^T r_s,  U = |theta|^2 / 2 - sum_s loglik_s.
+struct SliceGrad {
+    const NutsK& a;
+    template <int EPL>
+    __device__ __forceinline__ void operator()(int c, const WaveVec<EPL>& th, int lane, WaveVec<EPL>& g,
+                                               float& U) const
+    {
+        float ll = 0.0f;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) g.r[e] = 0.0f;
+        for (int s = 0; s < a.nslices; ++s) {
+            const float* gp = a.Gpart + ((size_t)s * a.m + c) * a.Dp;
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) g.r[e] += gp[e * 64 + lane];
+            ll += a.Upart[(size_t)s * a.m + c];
+        }
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) g.r[e] = th.r[e] - g.r[e];
+        U = uni(0.5f * wdot(th, th) - ll);
+    }
+};
+
+// Acceptance statistic of one leaf: min(1, e^w), w = H0 - H; a divergent or
+// undefined energy counts 0.
+__device__ __forceinline__ float nuts_leaf_accept(float w)
+{
+    if (w >= 0.0f) return 1.0f;
+    return w > -INFINITY ? expf(w) : 0.0f;
+}
+
+// The step on a chain's registers: finish the pending leapfrog with the
+// gradient `grad` supplies at its new position, then run the cheap states
+// until the next request.  Returns NutsChainBits.
+template <int EPL, class Grad>
+__device__ __forceinline__ int nuts_chain_body(const NutsK& a, const Grad& grad, int c, int lane, NutsScal& S)
+{
     float* Vc = a.V + (size_t)c * a.nvec * a.Dp;
     auto vec = [&](int i) { return Vc + (size_t)i * a.Dp; };
-    int k = uni(a.k[c]), j = uni(a.jd[c]), v = uni(a.v[c]), nn = uni(a.nn[c]), fl = uni(a.flags[c]),
-        nleap = uni(a.nleap[c]);
-    int64_t budget = uni((int64_t)a.budget[c]);
-    float H0 = uni(a.H0[c]), W = uni(a.W[c]), Ws = uni(a.Ws[c]), UP = uni(a.UP[c]), US = uni(a.US[c]);
+    uint32_t t = S.t;
+    int k = S.k, j = S.j, v = S.v, nn = S.nn, fl = S.fl, nleap = S.nleap;
+    int64_t budget = S.budget;
+    float H0 = S.H0, W = S.W, Ws = S.Ws, UP = S.UP, US = S.US, acc = S.acc;
     const bool release = a.mode != 0 && uni(a.wctr[(a.step + 2) % 3]) == 0u;
     const float he = 0.5f * a.eps;
     int req = 0;
@@ -88,24 +168,13 @@ __device__ __forceinline__ int nuts_chain_step(const NutsK& a, int c, int lane)
         ph.load(vec(V_PH), lane);
         th.load(vec(eth), lane);
         rs.load(vec(V_RHOS), lane);
-        // the gradient's row-slice partials, added in slice order:
-        // grad U = theta - sum_s X_s^T r_s,  U = |theta|^2 / 2 - sum_s loglik_s
-        float ll = 0.0f;
-#pragma unroll
-        for (int e = 0; e < EPL; ++e) g.r[e] = 0.0f;
-        for (int s = 0; s < a.nslices; ++s) {
-            const float* gp = a.Gpart + ((size_t)s * a.m + c) * a.Dp;
-#pragma unroll
-            for (int e = 0; e < EPL; ++e) g.r[e] += gp[e * 64 + lane];
-            ll += a.Upart[(size_t)s * a.m + c];
-        }
-#pragma unroll
-        for (int e = 0; e < EPL; ++e) g.r[e] = th.r[e] - g.r[e];
-        const float Un = uni(0.5f * wdot(th, th) - ll);
+        float Un;
+        grad(c, th, lane, g, Un);
 #pragma unroll
         for (int e = 0; e < EPL; ++e) p.r[e] = ph.r[e] - vhe * g.r[e];
         ++nleap;
         const float w = H0 - (Un + 0.5f * wdot(p, p));
+        acc += nuts_leaf_accept(w);
         p.store(vec(ep), lane);
         g.store(vec(eg), lane);
         if (!(-w <= kDeltaMax)) {
@@ -278,24 +347,50 @@ __device__ __forceinline__ int nuts_chain_step(const NutsK& a, int c, int lane)
         }
         break;
     }
-    if (lane == 0) {
-        a.t[c] = t;
-        a.k[c] = k;
-        a.jd[c] = j;
-        a.v[c] = v;
-        a.nn[c] = nn;
-        a.flags[c] = fl;
-        a.nleap[c] = nleap;
-        a.budget[c] = budget;
-        a.H0[c] = H0;
-        a.W[c] = W;
-        a.Ws[c] = Ws;
-        a.UP[c] = UP;
-        a.US[c] = US;
-        a.req[c] = req;
+    S.t = t;
+    S.k = k;
+    S.j = j;
+    S.v = v;
+    S.nn = nn;
+    S.fl = fl;
+    S.nleap = nleap;
+    S.budget = budget;
+    S.H0 = H0;
+    S.W = W;
+    S.Ws = Ws;
+    S.UP = UP;
+    S.US = US;
+    S.acc = acc;
+    const int rq = req ? NC_REQ : 0;
+    if (t >= a.tstop) return rq;
+    return rq | NC_ALIVE | ((a.mode != 0 && k != NS_WAIT) ? NC_INDRAW : 0);
+}
+
+// One runtime step of chain c (one wavefront) with its state in memory:
+// load, step, store.  Returns NC_ALIVE if the chain is short of tstop
+// afterwards, plus NC_INDRAW if it is also still inside its draw
+// (synchronized runtimes).  Gradient requests (the steps) are counted by the
+// compaction.
+template <int EPL, class Grad>
+__device__ __forceinline__ int nuts_chain_step(const NutsK& a, const Grad& grad, int c, int lane)
+{
+    c = uni(c);
+    const uint32_t t = uni(a.t[c]);
+    if (t >= a.tstop) {
+        if (lane == 0) a.req[c] = 0;
+        return 0;
     }
-    if (t >= a.tstop) return 0;
-    return NC_ALIVE | ((a.mode != 0 && k != NS_WAIT) ? NC_INDRAW : 0);
+    NutsScal S = nuts_load(a, c, t);
+    const int bits = nuts_chain_body<EPL>(a, grad, c, lane, S);
+    nuts_store(a, c, S, (bits & NC_REQ) ? 1 : 0, lane);
+    return bits & (NC_ALIVE | NC_INDRAW);
+}
+
+// Logistic regression (gradient from the row-slice partials).
+template <int EPL>
+__device__ __forceinline__ int nuts_chain_step(const NutsK& a, int c, int lane)
+{
+    return nuts_chain_step<EPL>(a, SliceGrad{a}, c, lane);
 }
 
 // Chains of one job that asked for a gradient, in chain order (one block of
@@ -386,6 +481,9 @@ inline NutsK nuts_view(const JobDev& j, int mode, uint32_t step)
     a.counts = j.counts;
     a.ctr = j.ctr;
     a.wctr = j.wctr;
+    a.acc = (float*)j.acc;
+    a.maxN = j.maxN;
+    a.queue = j.queue;
     return a;
 }
 

@@ -272,6 +272,10 @@ fsmmc_status fsmmc_server_submit(fsmmc_server* s, const fsmmc_target_spec* targe
     fsmmc_status st = validate_specs(target, sampler, n_chains, n_draws);
     if (st != FSMMC_OK) return st;
     if (sampler->dtype != FSMMC_F32) return fail(FSMMC_ENOTSUP, "served jobs are FP32");
+    if (sampler->kind == FSMMC_NUTS && target->kind != FSMMC_LOGREG)
+        return fail(FSMMC_ENOTSUP, "served NUTS jobs are LOGREG only");
+    if (sampler->kind == FSMMC_DRSYM || sampler->kind == FSMMC_SLICE)
+        return fail(FSMMC_ENOTSUP, "DRSYM and SLICE jobs are not served");
     SrvJob* sj = new SrvJob();
     sj->target = *target;
     sj->sampler = *sampler;

@@ -8,6 +8,10 @@
   initial monotone sequence estimator (Geyer 1992, Statist. Sci. 7) on the
   autocorrelation pooled over chains with the between/within-chain variance
   of Gelman et al. (BDA3, Sec. 11.5); chains x draws x coordinates at once.
+* ``moments``: per-coordinate mean and variance with their Monte Carlo
+  standard errors (sd / sqrt(ESS), the variance's from the ESS of the
+  squared deviations), and ``z_scores``: the difference of two such
+  estimates in units of their combined standard error.
 """
 from __future__ import annotations
 
@@ -57,3 +61,26 @@ def ess(draws):
         tau = max(tau, 1.0 / np.log10(m * n + 10.0))
         out[j] = m * n / tau
     return out
+
+
+def moments(draws, mcse_chains=1024):
+    """Mean, variance and their MCSEs per coordinate of draws (chains, n, k);
+    the ESS is estimated on the first mcse_chains chains and scaled to all."""
+    x = np.asarray(draws, dtype=np.float64)
+    if x.ndim == 2:
+        x = x[:, :, None]
+    m = x.shape[0]
+    c = min(m, mcse_chains)
+    mean = x.mean(axis=(0, 1))
+    var = x.var(axis=(0, 1))
+    sq = (x - mean) ** 2
+    e1 = ess(x[:c]) * (m / c)
+    e2 = ess(sq[:c]) * (m / c)
+    return dict(mean=mean, var=var, mean_mcse=np.sqrt(var / e1), var_mcse=sq.std(axis=(0, 1)) / np.sqrt(e2))
+
+
+def z_scores(a, b):
+    """Differences of two moments() results in units of their combined MCSE."""
+    zm = (a["mean"] - b["mean"]) / np.sqrt(a["mean_mcse"] ** 2 + b["mean_mcse"] ** 2)
+    zv = (a["var"] - b["var"]) / np.sqrt(a["var_mcse"] ** 2 + b["var_mcse"] ** 2)
+    return dict(mean_z=[float(v) for v in zm], var_z=[float(v) for v in zv])

@@ -16,8 +16,9 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libfsmmc.so")
 
 OK, EINVAL, ENOMEM, EBUDGET, EDEVICE, EBUSY, ENOTDONE, ENOTSUP = range(8)
-GP_GAUSS, GP_LOGISTIC, LOGREG, FUNNEL, GAUSS_DIAG = range(5)
-ESS, NUTS, DRMH = range(3)
+GP_GAUSS, GP_LOGISTIC, LOGREG, FUNNEL, GAUSS_DIAG, MOG = range(6)
+HIST_BINS = 1025
+ESS, NUTS, DRMH, DRSYM, SLICE = range(5)
 F32, F64 = 0, 1
 SYNC_VMAP, SYNC_COMPACT = 0, 1
 
@@ -45,19 +46,23 @@ class SamplerSpec(C.Structure):
 
 
 class Tune(C.Structure):
-    _fields_ = [("window", C.c_int32), ("timing", C.c_int32), ("reserved", C.c_int32 * 6)]
+    _fields_ = [("window", C.c_int32), ("timing", C.c_int32), ("fsm_states", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class Stats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("padded_steps", C.c_int64), ("draws", C.c_int64),
                 ("chains_done", C.c_int32), ("guard_trips", C.c_int32), ("launches", C.c_int32),
                 ("reserved", C.c_int32), ("kernel_ms", C.c_double * 4),
-                ("kernel_launches", C.c_int32 * 4)]
+                ("kernel_launches", C.c_int32 * 4), ("mean_loops", C.c_double),
+                ("mean_max_loops", C.c_double), ("r_hat", C.c_double), ("active_lanes", C.c_int64),
+                ("lane_slots", C.c_int64), ("accept_sum", C.c_double), ("hist", C.c_int64 * HIST_BINS)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
         d["kernel_ms"] = list(self.kernel_ms)
         d["kernel_launches"] = list(self.kernel_launches)
+        d["hist"] = np.frombuffer(self.hist, dtype=np.int64).copy()
         return d
 
 
@@ -302,6 +307,15 @@ def logreg_target(X, y):
     return spec, (X, y)
 
 
+def mog_target(means, log_weights, prec):
+    """Mixture of K Gaussians sharing the precision matrix prec (D x D):
+    means (K x D), log_weights (K,)."""
+    means, log_weights, prec = _dense(means), _dense(log_weights), _dense(prec)
+    spec = TargetSpec(MOG, int(means.shape[1]), int(means.shape[0]), 0, _ptr(means), _ptr(log_weights), None,
+                      _ptr(prec), 0.0)
+    return spec, (means, log_weights, prec)
+
+
 def nuts_sampler(step_size, max_depth=10, dtype=F32):
     return SamplerSpec(NUTS, dtype, int(max_depth), 0, float(step_size), (C.c_double * 4)())
 
@@ -317,6 +331,17 @@ def gauss_target(prec):
     return TargetSpec(GAUSS_DIAG, int(prec.numel()), 0, 0, None, None, None, _ptr(prec), 0.0), (prec,)
 
 
+def drsym_sampler(n_tries=100, sigma=0.1, dtype=F32):
+    """Symmetric delayed rejection: up to n_tries proposals per draw, each
+    re-centred on the last rejected one, standard deviation sigma."""
+    return SamplerSpec(DRSYM, dtype, 0, int(n_tries), 0.0, (C.c_double * 4)(float(sigma), 0.0, 0.0, 0.0))
+
+
+def slice_sampler(width=1.0, dtype=F32):
+    """Slice sampling along a random direction, stepping-out width `width`."""
+    return SamplerSpec(SLICE, dtype, 0, 0, 0.0, (C.c_double * 4)(float(width), 0.0, 0.0, 0.0))
+
+
 def dr_sampler(scales=(1.0, 0.3, 0.1), dtype=F32):
     sc = list(scales) + [0.0] * (4 - len(scales))
     return SamplerSpec(DRMH, dtype, 0, len(scales), 0.0, (C.c_double * 4)(*sc))
@@ -326,13 +351,13 @@ class Job:
     """One sampling job: n_chains chains x n_draws draws of one target."""
 
     def __init__(self, ctx, target, sampler, n_chains, n_draws, seed, x0=None, out=None,
-                 stream=None, window=0, timing=False):
+                 stream=None, window=0, timing=False, fsm_states=0):
         import torch
         spec, self._keep = target
         self.sampler = sampler
         self.m, self.n, self.dim = n_chains, n_draws, spec.dim
         self.dtype = torch.float32 if sampler.dtype == F32 else torch.float64
-        tune = Tune(window, 1 if timing else 0) if (window or timing) else None
+        tune = Tune(window, 1 if timing else 0, fsm_states) if (window or timing or fsm_states) else None
         torch.cuda.synchronize()
         # x0 is read asynchronously on the job's stream: keep a dense copy alive with the job
         self._x0 = _dense(x0)

@@ -53,3 +53,31 @@ def test_argument_errors_without_device_work():
     assert lib.fsmmc_ctx_destroy(None) == F.EINVAL
     assert lib.fsmmc_ctx_create(0, 0, None) == F.EINVAL
     assert F.version().startswith("fsmmc")
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    # sizes and field offsets of the ABI structs as a C compiler lays them out
+    import subprocess
+    from paper_2503_17405_amd import fsmmc as F
+    structs = {"fsmmc_target_spec": F.TargetSpec, "fsmmc_sampler_spec": F.SamplerSpec,
+               "fsmmc_tune": F.Tune, "fsmmc_stats": F.Stats, "fsmmc_batch_tune": F.BatchTune,
+               "fsmmc_batch_counters": F.BatchCounters, "fsmmc_server_config": F.ServerConfig,
+               "fsmmc_server_done": F.ServerDone, "fsmmc_server_counters": F.ServerCounters}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fsmmc.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    r = subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True,
+                                                       text=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got["%s.%s" % (cname, f)]) == getattr(py, f).offset, (cname, f)
