@@ -143,20 +143,73 @@ static int decide(int outcome, double margin, double scale)
 /* ------------------------------------------------------------------ */
 /* Targets.                                                            */
 enum { ORC_GP_GAUSS = 0, ORC_GP_LOGISTIC = 1, ORC_LOGREG = 2, ORC_FUNNEL = 3, ORC_GAUSS_DIAG = 4,
-       ORC_MOG = 5 };
+       ORC_MOG = 5, ORC_GP_HYPER = 6 };
 
 typedef struct {
     int32_t kind;
     int32_t dim;
-    int32_t n_data;     /* LOGREG: rows of X; MOG: number of components K      */
-    int32_t pad_;
+    int32_t n_data;     /* LOGREG: rows of X; MOG: number of components K;
+                           GP_HYPER: number of observations n                  */
+    int32_t aux;        /* GP_HYPER: input dimension p of the rows of X        */
     const double* X;    /* LOGREG: n_data x dim, row-major; MOG: K x dim means */
     const double* y;    /* GP: dim observations/labels; LOGREG: n_data labels;
                            MOG: K log mixture weights                          */
     const double* prec; /* GAUSS_DIAG: dim precisions; MOG: dim x dim shared
                            precision matrix (inverse covariance), row-major    */
-    double noise_sd;    /* GP_GAUSS observation noise standard deviation       */
+    double noise_sd;    /* GP_GAUSS observation noise standard deviation;
+                           GP_HYPER: jitter added to the diagonal              */
 } orc_target;
+
+/* GP regression marginal likelihood of the hyperparameters (Sec. 7.2):
+ * theta = (tau, lambda, sigma), k(a, b) = tau^2 exp(-lambda^2 |a - b|^2),
+ * y ~ N(0, C), C = tau^2 K + (sigma^2 + jitter) I.  Returns
+ * -y^T C^-1 y / 2 - log det C / 2 (no 2 pi term), -inf if C is not positive
+ * definite in floating point; *quad and *logdet receive the two terms.
+ * Cholesky C = L L^T row by row (Cholesky-Banachiewicz), forward solve
+ * L z = y, quad = |z|^2, log det = 2 sum log L_ii.                      */
+double orc_gp_hyper_loglik(const orc_target* t, const double* th, double* quad, double* logdet)
+{
+    int n = t->n_data, p = t->aux;
+    double tau2 = th[0] * th[0], lam2 = th[1] * th[1], s2 = th[2] * th[2] + t->noise_sd;
+    double* L = (double*)calloc((size_t)n * n, sizeof(double));
+    double* z = (double*)calloc((size_t)n, sizeof(double));
+    double ld = 0.0, q = 0.0;
+    int ok = 1;
+    for (int i = 0; i < n && ok; ++i) {
+        for (int k = 0; k <= i; ++k) {
+            double r2 = 0.0;
+            for (int d = 0; d < p; ++d) {
+                double e = t->X[(size_t)i * p + d] - t->X[(size_t)k * p + d];
+                r2 += e * e;
+            }
+            double c = tau2 * exp(-lam2 * r2) + (i == k ? s2 : 0.0);
+            for (int j = 0; j < k; ++j) c -= L[(size_t)i * n + j] * L[(size_t)k * n + j];
+            if (i == k) {
+                if (!(c > 0.0)) {
+                    ok = 0;
+                    break;
+                }
+                L[(size_t)i * n + i] = sqrt(c);
+            } else {
+                L[(size_t)i * n + k] = c / L[(size_t)k * n + k];
+            }
+        }
+    }
+    if (ok) {
+        for (int i = 0; i < n; ++i) {
+            double r = t->y[i];
+            for (int j = 0; j < i; ++j) r -= L[(size_t)i * n + j] * z[j];
+            z[i] = r / L[(size_t)i * n + i];
+            q += z[i] * z[i];
+            ld += 2.0 * log(L[(size_t)i * n + i]);
+        }
+    }
+    free(L);
+    free(z);
+    if (quad) *quad = ok ? q : INFINITY;
+    if (logdet) *logdet = ok ? ld : INFINITY;
+    return ok ? -0.5 * q - 0.5 * ld : -INFINITY;
+}
 
 static double softplus(double a) { return (a > 0.0 ? a : 0.0) + log1p(exp(-fabs(a))); }
 
@@ -171,6 +224,7 @@ static double sigmoid(double a)
 double orc_gp_loglik(const orc_target* t, const double* f)
 {
     double s = 0.0;
+    if (t->kind == ORC_GP_HYPER) return orc_gp_hyper_loglik(t, f, NULL, NULL);
     if (t->kind == ORC_GP_GAUSS) {
         double inv2v = 1.0 / (2.0 * t->noise_sd * t->noise_sd);
         for (int i = 0; i < t->dim; ++i) {
@@ -187,6 +241,11 @@ double orc_gp_loglik(const orc_target* t, const double* f)
 static double gp_loglik_absterms(const orc_target* t, const double* f)
 {
     double s = 0.0;
+    if (t->kind == ORC_GP_HYPER) {
+        double q = 0.0, ld = 0.0;
+        orc_gp_hyper_loglik(t, f, &q, &ld);
+        return 0.5 * fabs(q) + 0.5 * fabs(ld);
+    }
     if (t->kind == ORC_GP_GAUSS) {
         double inv2v = 1.0 / (2.0 * t->noise_sd * t->noise_sd);
         for (int i = 0; i < t->dim; ++i) {

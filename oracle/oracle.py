@@ -22,7 +22,7 @@ _SRC = os.path.join(_HERE, "fsmmc_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # target kinds
-GP_GAUSS, GP_LOGISTIC, LOGREG, FUNNEL, GAUSS_DIAG, MOG = 0, 1, 2, 3, 4, 5
+GP_GAUSS, GP_LOGISTIC, LOGREG, FUNNEL, GAUSS_DIAG, MOG, GP_HYPER = 0, 1, 2, 3, 4, 5, 6
 # sampler kinds
 ESS, NUTS, DRMH, DRSYM, SLICE = 0, 1, 2, 3, 4
 # stream roles
@@ -43,7 +43,7 @@ def build(force: bool = True) -> str:
 
 class _Target(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("n_data", C.c_int32),
-                ("pad_", C.c_int32), ("X", C.c_void_p), ("y", C.c_void_p),
+                ("aux", C.c_int32), ("X", C.c_void_p), ("y", C.c_void_p),
                 ("prec", C.c_void_p), ("noise_sd", C.c_double)]
 
 
@@ -76,6 +76,8 @@ def lib():
             L.orc_uniform.restype = d
             L.orc_uniform.argtypes = [u64, u32, u32, u32, u32]
             L.orc_normals.argtypes = [u64, u32, u32, u32, u32, i32, p]
+            L.orc_gp_hyper_loglik.restype = d
+            L.orc_gp_hyper_loglik.argtypes = [p, p, p, p]
             L.orc_gp_loglik.restype = d
             L.orc_gp_loglik.argtypes = [p, p]
             L.orc_potential.restype = d
@@ -130,7 +132,8 @@ class Target:
         self.kind, self.dim = kind, int(dim)
         self.X, self.y, self.prec = _f64(X), _f64(y), _f64(prec)
         n_data = 0 if self.X is None else self.X.shape[0]
-        self.s = _Target(kind, self.dim, n_data, 0, _ptr(self.X), _ptr(self.y), _ptr(self.prec),
+        aux = self.X.shape[1] if (self.X is not None and self.X.ndim == 2) else 0
+        self.s = _Target(kind, self.dim, n_data, aux, _ptr(self.X), _ptr(self.y), _ptr(self.prec),
                          float(noise_sd))
 
     @property
@@ -161,6 +164,17 @@ def mog_target(means, log_weights, prec):
     means = np.atleast_2d(np.asarray(means, dtype=np.float64))
     return Target(MOG, means.shape[1], X=means, y=np.asarray(log_weights, dtype=np.float64),
                   prec=np.asarray(prec, dtype=np.float64))
+
+
+def gp_hyper_target(X, y, jitter=1e-6):
+    """GP regression hyperparameters theta = (tau, lambda, sigma): the marginal
+    likelihood N(y; 0, tau^2 exp(-lambda^2 |a - b|^2) + (sigma^2 + jitter) I)."""
+    X = np.atleast_2d(np.asarray(X, dtype=np.float64))
+    return Target(GP_HYPER, 3, X=X, y=np.asarray(y, dtype=np.float64), noise_sd=jitter)
+
+
+def gp_hyper_loglik(target, th):
+    return lib().orc_gp_hyper_loglik(target.ref, _ptr(_f64(th)), None, None)
 
 
 def gauss_target(prec):

@@ -21,6 +21,10 @@ Workload recipes (the sizes the benchmark and tests use):
     Sigma^-1, the means and the log weights are rounded to FP32 so that every
     side reads the same numbers; starting points are exact draws from the
     mixture.
+  * ``gp_hyper``: GP regression data standing in for the paper's 6-feature
+    real-estate regression: n inputs uniform on [0, 1]^6, outputs
+    f(x) + 0.3 eps with f drawn from a GP with tau = 1, lambda = 1.5, then
+    standardised; starting hyperparameters drawn from the N(0, I) prior.
 """
 from __future__ import annotations
 
@@ -130,3 +134,17 @@ def mog(dim=100, rho=0.99, modes=(-10.0, 0.0, 10.0), n_chains=0, seed=6001):
         Z = g.standard_normal((n_chains, D))
         x0 = np.ascontiguousarray(means.astype(np.float64)[comp] + Z @ Lc.T)
     return dict(prec=prec32, means=means, log_weights=logw, cov=cov_r, x0=x0, rho=rho, modes=tuple(modes))
+
+
+def gp_hyper(n=100, p=6, n_chains=0, seed=9001):
+    """GP-regression data for the hyperparameter posterior; x0: prior draws."""
+    g = _rng(seed)
+    X = g.uniform(0.0, 1.0, size=(n, p))
+    d2 = ((X[:, None, :] - X[None, :, :]) ** 2).sum(axis=2)
+    K = np.exp(-(1.5 ** 2) * d2) + 1e-8 * np.eye(n)
+    f = np.linalg.cholesky(K) @ g.standard_normal(n)
+    y = f + 0.3 * g.standard_normal(n)
+    if n > 1:
+        y = (y - y.mean()) / y.std()
+    x0 = g.standard_normal((n_chains, 3)) if n_chains > 0 else None
+    return dict(X=X, y=y, x0=x0, jitter=1e-6)
