@@ -447,6 +447,55 @@ def bench_slice(F, ctx, args):
     return res
 
 
+def bench_gphyper(F, ctx, args):
+    """ESS on GP-regression hyperparameters (tau, lambda, sigma), N(0, I) prior,
+    marginal likelihood through an FP64 Cholesky of the n x n kernel matrix
+    inside every loop iteration; FSM vs synchronized for n in args.gph_obs."""
+    import torch
+
+    from paper_2503_17405_amd import inputs
+    res = dict(workload="ESS on GP-regression hyperparameters: n observations with 6 inputs (synthetic "
+                        "stand-in for the 6-feature regression data), N(0,I) prior on (tau, lambda, sigma), "
+                        "FP64 Cholesky per likelihood, %d chains x %d draws" % (args.gph_chains, args.gph_draws),
+               runs={})
+    m, n = args.gph_chains, args.gph_draws
+    for nobs in args.gph_obs:
+        w = inputs.gp_hyper(n=nobs, n_chains=m, seed=9001)
+        tg = F.gp_hyper_target(torch.tensor(w["X"], device="cuda"), torch.tensor(w["y"], device="cuda"),
+                               w["jitter"])
+        x0 = torch.tensor(w["x0"], device="cuda")
+        out = torch.empty((m, n, 3), dtype=torch.float64, device="cuda")
+        sampler = F.ess_sampler(F.F64)
+
+        def make():
+            return F.Job(ctx, tg, sampler, m, n, 9002, x0=x0, out=out)
+
+        log("GP hyper n=%d" % nobs)
+        t_fsm, job = timed_jobs(make, lambda j: j.step_fsm(0), 1, 1)
+        st = job.stats()
+        job.free()
+        ref = checksum(out.view(torch.float32))
+        r = dict(obs=nobs, seconds=t_fsm, draws_per_s=m * n / t_fsm, likelihoods=st["steps"],
+                 likelihoods_per_s=st["steps"] / t_fsm, cholesky_flop_per_likelihood=nobs ** 3 / 3.0,
+                 mean_loop=st["mean_loops"], mean_max_loop=st["mean_max_loops"], R_hat_m=st["r_hat"])
+        sync = {}
+        if not args.no_sync:
+            for name, mode in (("vmap", F.SYNC_VMAP), ("compact", F.SYNC_COMPACT)):
+                dt, job = timed_jobs(make, lambda j, mode=mode: j.step_synchronized(n, mode), 1, 0)
+                s2 = job.stats()
+                job.free()
+                sync[name] = dict(seconds=dt, draws_per_s=m * n / dt, padded=s2["padded_steps"],
+                                  bit_exact_vs_fsm=bool(checksum(out.view(torch.float32)) == ref),
+                                  speedup_fsm=dt / t_fsm)
+        r["sync"] = sync
+        log("  n=%d: FSM %.3f s, R(m) %.2f%s" % (nobs, t_fsm, st["r_hat"], "" if not sync else
+            ", vmap %.2fx, compact %.2fx" % (sync["vmap"]["speedup_fsm"], sync["compact"]["speedup_fsm"])))
+        res["runs"][str(nobs)] = r
+        del out
+        torch.cuda.empty_cache()
+    return res
+
+
 def _ess_job_data(F, D, ds, cache):
     import torch
 
@@ -691,6 +740,10 @@ def main():
     ap.add_argument("--no-slice", action="store_true")
     ap.add_argument("--slice-chains", type=int, nargs="+", default=[1024, 65536])
     ap.add_argument("--slice-draws", type=int, default=1000)
+    ap.add_argument("--no-gph", action="store_true")
+    ap.add_argument("--gph-obs", type=int, nargs="+", default=[25, 100])
+    ap.add_argument("--gph-chains", type=int, default=1024)
+    ap.add_argument("--gph-draws", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sync", action="store_true")
     ap.add_argument("--cpu-draws", type=int, default=2000)
@@ -740,6 +793,7 @@ def main():
         mog = bench_mog(F, ctx, args)
     drsym = None if args.no_drsym else bench_drsym(F, ctx, args)
     slc = None if args.no_slice else bench_slice(F, ctx, args)
+    gph = None if args.no_gph else bench_gphyper(F, ctx, args)
     batch = None
     if not args.no_batch:
         batch = bench_batch(F, ctx, args)
@@ -801,6 +855,7 @@ def main():
         "nuts_mog": mog,
         "drsym": drsym,
         "slice": slc,
+        "ess_gp_hyper": gph,
         "batch": batch,
         "serve": serve,
         "cpu_baseline": cpu,

@@ -58,8 +58,11 @@ typedef enum {
     FSMMC_LOGREG = 2,      /* Bayesian logistic regression, prior N(0, I)            */
     FSMMC_FUNNEL = 3,      /* Neal's funnel: v ~ N(0, 9), x_i | v ~ N(0, e^v)        */
     FSMMC_GAUSS_DIAG = 4,  /* N(0, diag(prec)^-1)                                    */
-    FSMMC_MOG = 5          /* mixture of K Gaussians sharing one covariance (Sec. 7.3):
+    FSMMC_MOG = 5,         /* mixture of K Gaussians sharing one covariance (Sec. 7.3):
                               pi(x) ∝ sum_k w_k exp(-(x - mu_k)^T P (x - mu_k) / 2)  */
+    FSMMC_GP_HYPER = 6     /* GP-regression hyperparameters theta = (tau, lambda, sigma),
+                              prior N(0, I), likelihood N(y; 0, tau^2 exp(-lambda^2
+                              |x_i - x_k|^2) + (sigma^2 + jitter) I) (Sec. 7.2); ESS, FP64 */
 } fsmmc_target_kind;
 
 /* Samplers (Sec. 3.1, Fig. "Finite state machines for the sample function"). */
@@ -91,17 +94,21 @@ typedef enum {
 typedef struct {
     int32_t kind;     /* fsmmc_target_kind                                         */
     int32_t dim;      /* d >= 1                                                    */
-    int32_t n_data;   /* LOGREG: number of rows of X; MOG: components K in [1, 8]   */
-    int32_t reserved; /* must be 0                                                 */
-    const void* X;    /* LOGREG: n_data x dim design matrix; MOG: K x dim means mu_k */
+    int32_t n_data;   /* LOGREG: number of rows of X; MOG: components K in [1, 8];
+                         GP_HYPER: observations n in [1, 128]                     */
+    int32_t aux;      /* GP_HYPER: input dimension p in [1, 16]; otherwise 0       */
+    const void* X;    /* LOGREG: n_data x dim design matrix; MOG: K x dim means mu_k;
+                         GP_HYPER: n_data x aux inputs                            */
     const void* y;    /* GP: dim observations (GAUSS) or labels in {0,1} (LOGISTIC);
-                         LOGREG: n_data labels in {0,1}; MOG: K log weights log w_k */
+                         LOGREG: n_data labels in {0,1}; MOG: K log weights log w_k;
+                         GP_HYPER: n_data outputs                                */
     const void* chol_L; /* GP: dim x dim lower Cholesky factor of the prior covariance
                            (entries above the diagonal are ignored)                */
     const void* prec; /* GAUSS_DIAG: dim precisions; MOG: dim x dim precision
                          matrix P (symmetric positive definite), shared by all
                          components                                            */
-    double noise_sd;  /* GP_GAUSS: observation noise standard deviation            */
+    double noise_sd;  /* GP_GAUSS: observation noise standard deviation;
+                         GP_HYPER: jitter added to the diagonal (>= 0)            */
 } fsmmc_target_spec;
 
 /* Sampler description. */

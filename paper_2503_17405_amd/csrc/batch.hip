@@ -533,6 +533,8 @@ fsmmc_status batch_admissible(const fsmmc_batch* b, const fsmmc_job* j)
     if (j->d.dtype != FSMMC_F32) return fail(FSMMC_ENOTSUP, "batches run FP32 jobs");
     if (j->d.kind == FSMMC_NUTS && j->d.target != FSMMC_LOGREG)
         return fail(FSMMC_ENOTSUP, "batches run NUTS on LOGREG targets only");
+    if (j->d.kind == FSMMC_ESS && j->d.target == FSMMC_GP_HYPER)
+        return fail(FSMMC_ENOTSUP, "batches do not run GP_HYPER jobs");
     if (j->d.kind == FSMMC_DRSYM || j->d.kind == FSMMC_SLICE)
         return fail(FSMMC_ENOTSUP, "batches do not run DRSYM or SLICE jobs");
     return FSMMC_OK;

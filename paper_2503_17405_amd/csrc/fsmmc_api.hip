@@ -237,9 +237,19 @@ fsmmc_status fsmmc::validate_specs(const fsmmc_target_spec* t, const fsmmc_sampl
     if (m < 1) return fail(FSMMC_EINVAL, "n_chains must be >= 1");
     if (n < 1) return fail(FSMMC_EINVAL, "n_draws must be >= 1");
     if (t->dim < 1) return fail(FSMMC_EINVAL, "dim must be >= 1");
-    if (t->reserved != 0) return fail(FSMMC_EINVAL, "reserved field must be 0");
+    if (t->kind != FSMMC_GP_HYPER && t->aux != 0) return fail(FSMMC_EINVAL, "aux must be 0 for this target");
     if (s->dtype != FSMMC_F32 && s->dtype != FSMMC_F64) return fail(FSMMC_EINVAL, "bad dtype");
     if ((int64_t)m * (int64_t)n > (int64_t)1 << 31) return fail(FSMMC_EINVAL, "n_chains * n_draws too large");
+    if (s->kind == FSMMC_ESS && t->kind == FSMMC_GP_HYPER) {
+        if (s->dtype != FSMMC_F64) return fail(FSMMC_ENOTSUP, "GP_HYPER runs in FP64");
+        if (t->dim != 3) return fail(FSMMC_EINVAL, "GP_HYPER has dim 3 (tau, lambda, sigma)");
+        if (!t->X || !t->y) return fail(FSMMC_EINVAL, "GP_HYPER needs X and y");
+        if (t->n_data < 1 || t->n_data > gph_max_obs())
+            return fail(FSMMC_ENOTSUP, "GP_HYPER needs 1 to 128 observations");
+        if (t->aux < 1 || t->aux > gph_max_inputs()) return fail(FSMMC_EINVAL, "GP_HYPER input dimension must be in [1, 16]");
+        if (!(t->noise_sd >= 0.0) || !std::isfinite(t->noise_sd)) return fail(FSMMC_EINVAL, "jitter must be >= 0");
+        return FSMMC_OK;
+    }
     if (s->kind == FSMMC_ESS) {
         if (t->kind != FSMMC_GP_GAUSS && t->kind != FSMMC_GP_LOGISTIC)
             return fail(FSMMC_EINVAL, "ESS needs a GP target");
@@ -403,7 +413,27 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
     }
     d.tstop = (uint32_t)d.n;
 
-    if (d.kind == FSMMC_ESS) {
+    if (d.kind == FSMMC_ESS && d.target == FSMMC_GP_HYPER) {  // wave per chain, FP64, in-wave Cholesky
+        d.Dp = d.D;
+        d.N = target->n_data;
+        d.pdim = target->aux;
+        ALLOC(d.x, m * 3 * 8);
+        ALLOC(d.V, m * 3 * 8);
+        ALLOC(d.theta, m * 8);
+        ALLOC(d.tmin, m * 8);
+        ALLOC(d.tmax, m * 8);
+        ALLOC(d.logu, m * 8);
+        ALLOC(d.sink, m * 8);
+        ALLOC(d.maxN, (size_t)d.n * 4);
+        ALLOC(d.queue, 64);
+        ALLOC(d.X, (size_t)d.N * d.pdim * 8);
+        ALLOC(d.y, (size_t)d.N * 8);
+        HIP_TRY_JOB(hipMemcpyAsync(d.X, target->X, (size_t)d.N * d.pdim * 8, hipMemcpyDeviceToDevice, job->stream));
+        HIP_TRY_JOB(hipMemcpyAsync(d.y, target->y, (size_t)d.N * 8, hipMemcpyDeviceToDevice, job->stream));
+        HIP_TRY_JOB(gph_setup(d));
+        HIP_TRY_JOB(gph_init_state(d, x0, job->stream));
+        job->launches += x0 ? 2 : 1;
+    } else if (d.kind == FSMMC_ESS) {
         d.EPL = ess_supported_epl(d.D, d.dtype);
         d.Dp = 64 * d.EPL;
         const size_t Dp = (size_t)d.Dp;
@@ -448,6 +478,11 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
         job->launches += x0 ? 2 : 3;
     } else if (d.kind == FSMMC_SLICE) {  // lane per chain, [d][chain] state
         d.Dp = d.D;
+        // direction window: W draws per chain, at most 32 and 256 MiB
+        d.W = std::max(1, std::min(32, d.n));
+        while (d.W > 1 && (double)m * d.W * d.D * 4 > 268435456.0) d.W /= 2;
+        ALLOC(d.nu, m * (size_t)d.W * d.D * 4);
+        ALLOC(d.tsnap, m * 4);
         ALLOC(d.x, m * (size_t)d.D * 4);
         ALLOC(d.V, 2 * m * (size_t)d.D * 4);
         ALLOC(d.logu, m * 4);
@@ -696,6 +731,47 @@ static fsmmc_status mog_sync(fsmmc_job* job, int mode, uint32_t t0, uint32_t t1,
     return FSMMC_OK;
 }
 
+// ESS on GP hyperparameters: FSM = one persistent launch; synchronized = one
+// launch per draw (plus the vmap padding launch).
+static fsmmc_status gph_fsm(fsmmc_job* job, int64_t max_steps, int32_t* all_done)
+{
+    JobDev& d = job->d;
+    d.tstop = (uint32_t)d.n;
+    HIP_TRY(fill_i64(d.budget, max_steps > 0 ? max_steps : INT64_MAX, d.m, job->stream));
+    job->launches++;
+    HIP_TRY(launch(job, KC_FSM, [&] { return gph_run(d, 0, 0, &job->qticket, job->stream); }));
+    std::vector<uint32_t> t;
+    fsmmc_status s = progress(job, t, nullptr);
+    if (s != FSMMC_OK) return s;
+    harvest(job);
+    if (all_done) {
+        int done = 1;
+        for (uint32_t v : t) done &= v >= (uint32_t)d.n;
+        *all_done = done;
+    }
+    return FSMMC_OK;
+}
+
+static fsmmc_status gph_sync(fsmmc_job* job, int mode, uint32_t t0, uint32_t t1, int32_t* all_done)
+{
+    JobDev& d = job->d;
+    HIP_TRY(fill_i64(d.budget, INT64_MAX, d.m, job->stream));
+    job->launches++;
+    for (uint32_t dr = t0; dr < t1; ++dr) {
+        HIP_TRY(launch(job, KC_SYNC, [&] { return gph_run(d, 1, dr, &job->qticket, job->stream); }));
+        if (mode == FSMMC_SYNC_VMAP)
+            HIP_TRY(launch(job, KC_PAD, [&] { return gph_run(d, 2, dr, &job->qticket, job->stream); }));
+    }
+    std::vector<uint32_t> t;
+    fsmmc_status s = progress(job, t, nullptr);
+    if (s != FSMMC_OK) return s;
+    harvest(job);
+    for (uint32_t v : t)
+        if (v != t1) return fail(FSMMC_EDEVICE, "synchronized ESS: a chain did not complete its draw");
+    if (all_done) *all_done = t1 >= (uint32_t)d.n ? 1 : 0;
+    return FSMMC_OK;
+}
+
 // ESS windows [t0 + kW, t0 + (k+1)W): while window k is stepped on the job's
 // stream, the ellipse GEMM of window k+1 runs on the side stream from a
 // snapshot of the draw counters taken at the start of window k (every chain
@@ -744,16 +820,30 @@ fsmmc_status fsmmc_step_fsm(fsmmc_job* job, int64_t max_steps, int32_t* all_done
     JobDev& d = job->d;
     HIP_TRY(hipSetDevice(job->ctx->device));
     if (d.kind == FSMMC_NUTS && d.target == FSMMC_MOG) return mog_fsm(job, max_steps, all_done);
+    if (d.kind == FSMMC_ESS && d.target == FSMMC_GP_HYPER) return gph_fsm(job, max_steps, all_done);
     if (d.kind == FSMMC_NUTS) return nuts_run(job, 0, max_steps, (uint32_t)d.n, all_done);
-    if (d.kind == FSMMC_DRSYM || d.kind == FSMMC_SLICE) {
+    if (d.kind == FSMMC_SLICE) {  // window by window: directions, then the FSM kernel
+        d.tstop = (uint32_t)d.n;
+        HIP_TRY(fill_i64(d.budget, max_steps > 0 ? max_steps : INT64_MAX, d.m, job->stream));
+        job->launches++;
+        for (;;) {
+            HIP_TRY(hipMemsetAsync(d.ctr + 3, 0, 2 * sizeof(unsigned long long), job->stream));
+            HIP_TRY(launch(job, KC_G, [&] { return sl_dir_window(d, job->stream); }));
+            HIP_TRY(launch(job, KC_FSM, [&] { return sl_fsm_round(d, job->stream); }));
+            fsmmc_status s = read_ctr(job);
+            if (s != FSMMC_OK) return s;
+            if (job->h_ctr[3] == 0) break;  // no chain short of n with budget left
+        }
+        if (all_done) *all_done = job->h_ctr[4] == 0 ? 1 : 0;
+        return FSMMC_OK;
+    }
+    if (d.kind == FSMMC_DRSYM) {
         d.tstop = (uint32_t)d.n;
         const int64_t b = max_steps > 0 ? max_steps : INT64_MAX;
         HIP_TRY(fill_i64(d.budget, b, d.m, job->stream));
         job->launches++;
         HIP_TRY(hipMemsetAsync(d.ctr + 3, 0, 2 * sizeof(unsigned long long), job->stream));
-        HIP_TRY(launch(job, KC_FSM, [&] {
-            return d.kind == FSMMC_SLICE ? sl_fsm_round(d, job->stream) : drs_fsm_round(d, job->stream);
-        }));
+        HIP_TRY(launch(job, KC_FSM, [&] { return drs_fsm_round(d, job->stream); }));
         fsmmc_status s = read_ctr(job);
         if (s != FSMMC_OK) return s;
         if (all_done) *all_done = job->h_ctr[4] == 0 ? 1 : 0;
@@ -840,9 +930,18 @@ fsmmc_status fsmmc_step_synchronized(fsmmc_job* job, int32_t n_draws, int32_t mo
         if (d.target == FSMMC_MOG) return mog_sync(job, mode, t0, t1, all_done);
         return nuts_run(job, mode == FSMMC_SYNC_VMAP ? 1 : 2, 0, t1, all_done);
     }
+    if (d.kind == FSMMC_ESS && d.target == FSMMC_GP_HYPER) {
+        if (t1 == t0) {
+            if (all_done) *all_done = t1 >= (uint32_t)d.n ? 1 : 0;
+            return FSMMC_OK;
+        }
+        return gph_sync(job, mode, t0, t1, all_done);
+    }
     if (d.kind == FSMMC_DRSYM || d.kind == FSMMC_SLICE) {
         const bool sl = d.kind == FSMMC_SLICE;
         for (uint32_t dr = t0; dr < t1; ++dr) {
+            if (sl && (dr - t0) % (uint32_t)d.W == 0)
+                HIP_TRY(launch(job, KC_G, [&] { return sl_dir_window(d, job->stream); }));
             HIP_TRY(launch(job, KC_SYNC, [&] {
                 return sl ? sl_sync_draw(d, dr, job->stream) : drs_sync_draw(d, dr, job->stream);
             }));

@@ -21,7 +21,8 @@ struct JobDev {
     int target = 0;  // target kind
     int dtype = 0;
     int m = 0, n = 0, D = 0, Dp = 0, EPL = 0;
-    int N = 0, Np = 0;  // LOGREG rows (padded)
+    int N = 0, Np = 0;  // LOGREG rows (padded); GP_HYPER observations
+    int pdim = 0;       // GP_HYPER input dimension
     uint64_t seed = 0;
     double noise_sd = 0;
     double step_size = 0;
@@ -125,9 +126,18 @@ hipError_t mog_pad(const JobDev& j, uint32_t draw, unsigned long long* ticket, h
 // U and grad U at n points (n x D, row-major) into G (n x D, or NULL) and U (n).
 hipError_t mog_eval(const JobDev& j, int n, const float* pts, float* G, float* U, hipStream_t s);
 
+// ESS on GP-regression hyperparameters (gph.hip); mode 0 FSM, 1 one synchronized
+// draw, 2 vmap padding of that draw
+int gph_max_obs();
+int gph_max_inputs();
+hipError_t gph_setup(JobDev& j);
+hipError_t gph_init_state(const JobDev& j, const void* x0, hipStream_t s);
+hipError_t gph_run(const JobDev& j, int mode, uint32_t draw, unsigned long long* ticket, hipStream_t s);
+
 // Slice sampler launchers (slice.hip)
 hipError_t sl_init_state(const JobDev& j, const void* x0, hipStream_t s);
-hipError_t sl_fsm_round(const JobDev& j, hipStream_t s);
+hipError_t sl_dir_window(const JobDev& j, hipStream_t s);  // directions of every chain's next W draws
+hipError_t sl_fsm_round(const JobDev& j, hipStream_t s);   // one window
 hipError_t sl_sync_draw(const JobDev& j, uint32_t draw, hipStream_t s);
 hipError_t sl_pad_draw(const JobDev& j, uint32_t draw, hipStream_t s);
 

@@ -274,6 +274,7 @@ fsmmc_status fsmmc_server_submit(fsmmc_server* s, const fsmmc_target_spec* targe
     if (sampler->dtype != FSMMC_F32) return fail(FSMMC_ENOTSUP, "served jobs are FP32");
     if (sampler->kind == FSMMC_NUTS && target->kind != FSMMC_LOGREG)
         return fail(FSMMC_ENOTSUP, "served NUTS jobs are LOGREG only");
+    if (target->kind == FSMMC_GP_HYPER) return fail(FSMMC_ENOTSUP, "GP_HYPER jobs are not served");
     if (sampler->kind == FSMMC_DRSYM || sampler->kind == FSMMC_SLICE)
         return fail(FSMMC_ENOTSUP, "DRSYM and SLICE jobs are not served");
     SrvJob* sj = new SrvJob();

@@ -16,7 +16,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libfsmmc.so")
 
 OK, EINVAL, ENOMEM, EBUDGET, EDEVICE, EBUSY, ENOTDONE, ENOTSUP = range(8)
-GP_GAUSS, GP_LOGISTIC, LOGREG, FUNNEL, GAUSS_DIAG, MOG = range(6)
+GP_GAUSS, GP_LOGISTIC, LOGREG, FUNNEL, GAUSS_DIAG, MOG, GP_HYPER = range(7)
 HIST_BINS = 1025
 ESS, NUTS, DRMH, DRSYM, SLICE = range(5)
 F32, F64 = 0, 1
@@ -36,7 +36,7 @@ EXPORTS = [
 
 class TargetSpec(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("n_data", C.c_int32),
-                ("reserved", C.c_int32), ("X", C.c_void_p), ("y", C.c_void_p),
+                ("aux", C.c_int32), ("X", C.c_void_p), ("y", C.c_void_p),
                 ("chol_L", C.c_void_p), ("prec", C.c_void_p), ("noise_sd", C.c_double)]
 
 
@@ -314,6 +314,15 @@ def mog_target(means, log_weights, prec):
     spec = TargetSpec(MOG, int(means.shape[1]), int(means.shape[0]), 0, _ptr(means), _ptr(log_weights), None,
                       _ptr(prec), 0.0)
     return spec, (means, log_weights, prec)
+
+
+def gp_hyper_target(X, y, jitter=1e-6):
+    """GP-regression hyperparameters (tau, lambda, sigma) with the N(0, I)
+    prior: X (n x p) inputs and y (n,) outputs, FP64 device tensors."""
+    X, y = _dense(X), _dense(y)
+    spec = TargetSpec(GP_HYPER, 3, int(X.shape[0]), int(X.shape[1]), _ptr(X), _ptr(y), None, None,
+                      float(jitter))
+    return spec, (X, y)
 
 
 def nuts_sampler(step_size, max_depth=10, dtype=F32):
