@@ -45,9 +45,9 @@ sys.path.insert(0, ROOT)
 METRIC = "draws/sec FSM vs synchronized (ESS, NUTS, 8192 chains); p50/p99 job latency"
 PEAK_MFMA_F32 = 157.3  # TFLOP/s, MI355X dense FP32 MFMA
 PEAK_MFMA_BF16 = 2500.0  # TFLOP/s, MI355X dense bf16 MFMA
-# The D = 1024 ellipse GEMM computes each FP32 product as six bf16 piece products
-# (exact three-piece splits of both operands), so its ceiling in FP32-equivalent
-# flops is the bf16 peak over six.
+# The D = 1024 ellipse GEMM and the NUTS gradient compute each FP32 product as
+# six bf16 piece products (exact three-piece splits of both operands), so their
+# ceiling in FP32-equivalent flops is the bf16 peak over six.
 PIECE_PRODUCTS = 6
 PEAK_GEMM = PEAK_MFMA_BF16 / PIECE_PRODUCTS
 
@@ -250,9 +250,15 @@ def bench_nuts(F, ctx, args):
     res["effective"] = ess_report(out, t_fsm)
     g_ms = st["kernel_ms"][0]
     flops = 4.0 * N * D * st["steps"]  # X Theta and X^T r per requested gradient
-    res["gradient"] = dict(kernel="logreg_grad_kernel<4>", ms=g_ms,
+    g_tf = flops / (g_ms * 1e-3) / 1e12
+    res["gradient"] = dict(kernel="logreg_grad_bf16_kernel<4, 13>", ms=g_ms,
                            launches=st["kernel_launches"][0],
-                           tflops=flops / (g_ms * 1e-3) / 1e12, flop_per_gradient=4 * N * D)
+                           avg_us=g_ms * 1e3 / max(1, st["kernel_launches"][0]),
+                           tflops=g_tf, flop_per_gradient=4 * N * D,
+                           roofline=dict(bound="mfma", achieved=g_tf, peak=PEAK_GEMM, unit="TFLOP/s",
+                                         frac=g_tf / PEAK_GEMM,
+                                         note="FP32 products run as six bf16 piece products: ceiling "
+                                              "2500 / 6 TFLOP/s (FP32 MFMA peak 157.3 for scale)"))
     sync = {}
     if not args.no_sync:
         for name, mode in (("vmap", F.SYNC_VMAP), ("compact", F.SYNC_COMPACT)):

@@ -182,12 +182,13 @@ __global__ __launch_bounds__(1024) void batch_nuts_compact_kernel(const BJob* jo
 }
 
 template <int DT>
-__global__ __launch_bounds__(256) void batch_grad_kernel(const BJob* jobs_in, const BGrad* tiles)
+__global__ __launch_bounds__(512) void batch_grad_kernel(const BJob* jobs_in, const BGrad* tiles)
 {
+    extern __shared__ __align__(16) unsigned char lds[];
     const ConstBJob* jobs = (const ConstBJob*)jobs_in;
     const BGrad t = tiles[blockIdx.x];
     const GradK& a = *(const GradK*)&jobs[t.job].grad;
-    logreg_grad_tile<DT>(a, t.ct, t.sl);
+    logreg_grad_tile<DT>(a, t.ct, t.sl, lds);
 }
 
 // Block i: job i's chains short of n and its draws so far.
@@ -364,7 +365,7 @@ fsmmc_status rebuild(fsmmc_batch* b)
             J.cls = BC_NUTS;
             const int e = d.EPL == 1 ? 0 : 1;
             for (int c = 0; c < d.m; ++c) nsteps[e].push_back(BItem{i, c});
-            for (int ct = 0; ct * 64 < d.m; ++ct)
+            for (int ct = 0; ct * 128 < d.m; ++ct)
                 for (int sl = 0; sl < d.nslices; ++sl) grads[e].push_back(BGrad{i, ct, sl, 0});
             njobs.push_back(i);
         }
@@ -446,10 +447,10 @@ fsmmc_status rebuild(fsmmc_batch* b)
                            (const int32_t*)b->d_njobs);
         chk();
         if (b->grad_cnt[0])
-            hipLaunchKernelGGL(batch_grad_kernel<2>, dim3(b->grad_cnt[0]), dim3(256), 0, s, jobs,
+            hipLaunchKernelGGL(batch_grad_kernel<2>, dim3(b->grad_cnt[0]), dim3(512), GradB<2>::LDS, s, jobs,
                                (const BGrad*)b->d_grads);
         if (b->grad_cnt[1])
-            hipLaunchKernelGGL(batch_grad_kernel<4>, dim3(b->grad_cnt[1]), dim3(256), 0, s, jobs,
+            hipLaunchKernelGGL(batch_grad_kernel<4>, dim3(b->grad_cnt[1]), dim3(512), GradB<4>::LDS, s, jobs,
                                (const BGrad*)b->d_grads + b->grad_cnt[0]);
         chk();
     }
@@ -516,6 +517,10 @@ fsmmc_status batch_setup(fsmmc_batch* b, fsmmc_ctx* ctx, void* stream, const fsm
     }
     HIP_TRY(hipEventCreate(&b->e0));
     HIP_TRY(hipEventCreate(&b->e1));
+    HIP_TRY(hipFuncSetAttribute((const void*)batch_grad_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                GradB<2>::LDS));
+    HIP_TRY(hipFuncSetAttribute((const void*)batch_grad_kernel<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                GradB<4>::LDS));
     int nb0 = 0, nb1 = 0, cus = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb0, batch_fsm_kernel<false>, 256, 0));
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, batch_fsm_kernel<true>, 256, 0));

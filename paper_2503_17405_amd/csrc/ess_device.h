@@ -182,22 +182,6 @@ __device__ __forceinline__ void nu_gemm_block_flat(const NuK<float>& a, int col0
     }
 }
 
-// x = hi + mid + lo exactly, each piece a bf16 bit pattern: hi keeps the top 16
-// bits of x, the remainder x - hi (at most 16 significant bits) is exact in
-// FP32, mid keeps its top 16 bits and the rest (at most 8 significant bits)
-// is lo.  The host splits L the same way.
-__device__ __forceinline__ void split_bf16x3(float x, uint32_t& hi, uint32_t& mid, uint32_t& lo)
-{
-    const uint32_t uh = __float_as_uint(x) & 0xFFFF0000u;
-    const float r1 = x - __uint_as_float(uh);
-    const uint32_t um = __float_as_uint(r1) & 0xFFFF0000u;
-    const float r2 = r1 - __uint_as_float(um);
-    hi = uh >> 16;
-    mid = um >> 16;
-    lo = __float_as_uint(r2) >> 16;
-}
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // The 2- to 4-tile shapes (Dp > 256) on the bf16 matrix cores.  z and L are split

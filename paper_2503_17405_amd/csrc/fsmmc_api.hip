@@ -578,13 +578,14 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
         d.Dp = 64 * d.EPL;
         const size_t Dp = (size_t)d.Dp;
         d.N = target->n_data;
-        // Row slices of the gradient: about 1024 (chain tile, slice) blocks at full
-        // load -- two rounds of the blocks the chip holds at once -- with slices of
-        // 256 .. 1280 rows, a multiple of the 32-row chunk (measured at N = 10^4,
-        // m = 8192: 8 slices of 1280 rows beat 20 of 512 by 5%, 5 of 2048 lose 9%)
+        // Row slices of the gradient: about 512 (128-chain tile, slice) blocks at
+        // full load -- two rounds of the blocks the chip holds at once -- with
+        // slices of 256 .. 1280 rows, a multiple of the 32-row chunk (measured
+        // with the FP32 tile at N = 10^4, m = 8192: 8 slices of 1280 rows beat 20
+        // of 512 by 5%, 5 of 2048 lose 9%)
         {
-            const int tiles = (m + 63) / 64;
-            const int want = std::max(1, (1024 + tiles - 1) / tiles);
+            const int tiles = (m + 127) / 128;
+            const int want = std::max(1, (512 + tiles - 1) / tiles);
             const int rows = ((d.N + want - 1) / want + 31) / 32 * 32;
             d.slice_rows = std::min(1280, std::max(256, rows));
         }
@@ -609,10 +610,12 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
         ALLOC(d.Upart, (size_t)d.nslices * m * 4);
         ALLOC(d.wctr, 64);
         ALLOC(d.X, (size_t)d.Np * Dp * 4);
+        ALLOC(d.Xb, logreg_split_bytes(d));
         ALLOC(d.y, (size_t)d.Np * 4);
         HIP_TRY_JOB(hipMemcpy2DAsync(d.X, Dp * 4, target->X, (size_t)d.D * 4, (size_t)d.D * 4, (size_t)d.N,
                                      hipMemcpyDeviceToDevice, job->stream));
         HIP_TRY_JOB(hipMemcpyAsync(d.y, target->y, (size_t)d.N * 4, hipMemcpyDeviceToDevice, job->stream));
+        HIP_TRY_JOB(logreg_setup(d, job->stream));
         hipLaunchKernelGGL(fill_i32_kernel, dim3((d.m + 255) / 256), dim3(256), 0, job->stream, d.k, 1, d.m);
         HIP_TRY_JOB(hipGetLastError());
         HIP_TRY_JOB(nuts_init_state(d, x0, job->stream));

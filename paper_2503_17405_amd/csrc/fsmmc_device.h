@@ -267,4 +267,21 @@ struct Pi<double> {
     static constexpr double two_pi = 6.28318530717958647692;
 };
 
+// x = hi + mid + lo exactly, each piece a bf16 bit pattern: hi keeps the top 16
+// bits of x, the remainder x - hi (at most 16 significant bits) is exact in
+// FP32, mid keeps its top 16 bits and the rest (at most 8 significant bits)
+// is lo.  Host-side splits follow the same rule.
+__device__ __forceinline__ void split_bf16x3(float x, uint32_t& hi, uint32_t& mid, uint32_t& lo)
+{
+    const uint32_t uh = __float_as_uint(x) & 0xFFFF0000u;
+    const float r1 = x - __uint_as_float(uh);
+    const uint32_t um = __float_as_uint(r1) & 0xFFFF0000u;
+    const float r2 = r1 - __uint_as_float(um);
+    hi = uh >> 16;
+    mid = um >> 16;
+    lo = __float_as_uint(r2) >> 16;
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
 }  // namespace fsmmc

@@ -35,6 +35,7 @@ struct JobDev {
     void* Lp = nullptr; // FP32 GP with Dp > 256: L's bf16 pieces, packed (ess_lower_pieces_halfwords)
     void* y = nullptr;  // Dp (GP) or Np (LOGREG) labels / observations
     void* X = nullptr;  // LOGREG: Np x Dp, zero padded
+    void* Xb = nullptr; // LOGREG: X as three bf16 pieces, row- and d-major per 32-row chunk (logreg.hip)
     void* prec = nullptr;
 
     // common chain state
@@ -111,6 +112,8 @@ int nuts_nvec(int max_depth);
 hipError_t nuts_init_state(const JobDev& j, const void* x0, hipStream_t s);
 hipError_t nuts_transition(const JobDev& j, int mode, uint32_t step, hipStream_t s);
 hipError_t nuts_gradient(const JobDev& j, hipStream_t s);
+size_t logreg_split_bytes(const JobDev& j);
+hipError_t logreg_setup(const JobDev& j, hipStream_t s);
 hipError_t nuts_gradient_dense(const JobDev& j, int ncols, float* Gout, float* Uout, int gstride, hipStream_t s);
 
 // NUTS on a Gaussian mixture (mog.hip): P (Dp x Dp) in d.prec, means in d.X

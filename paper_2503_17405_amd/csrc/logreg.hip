@@ -4,31 +4,65 @@
 //   grad U = Theta - X^T r,  U = |Theta|^2 / 2 - sum_i [y_i eta_i - softplus(eta_i)].
 // This is the amortized g of the NUTS FSM (one evaluation per step per chain).
 //
-// logreg_grad_kernel: block = 4 waves, 64 listed chains x one row slice of the job.
-// Theta (64 x Dp) is staged in LDS once.  The slice is walked in chunks of 32
-// rows; each chunk of X is loaded once (coalesced float4, double-buffered:
-// the next chunk's loads are issued before this chunk's MFMAs) and shared by
-// the four waves:
-//   1. eta (32 rows x 64 chains) on v_mfma_f32_16x16x4_f32 with K = D rounded
-//      up to 4 (not the padded Dp): wave w owns rows 16 (w & 1) .. +15 and
-//      chains 32 (w >> 1) .. +31 (two 16 x 16 tiles);
-//   2. r = y - sigmoid(eta) written to LDS, and the log-likelihood with one
-//      log per four rows (the log of the product of the factors 1 + e^-|eta|);
-//   3. X_chunk^T r on v_mfma_f32_16x16x4_f32 in 16-row tiles of d (D rounded
-//      up to 16): wave w owns chains 16 w .. +15 and every d tile, so partial
-//      gradients never need a cross-wave reduction.
-// Row slices are added in slice order (by the NUTS transition that consumes
-// the gradient, or by logreg_reduce_kernel for the starting points); no float
-// atomics, so every result is reproducible bit for bit.
+// logreg_grad_bf16_kernel: block = 8 waves, 128 listed chains x one row slice
+// of the job, on the bf16 matrix cores with FP32 results.  Every FP32 operand
+// is split exactly into three bf16 pieces (hi + mid + lo, split_bf16x3) and a
+// product is the sum of the six piece products that carry its first ~24 bits
+// (lo*hi, mid*mid, hi*lo, mid*hi, hi*mid, hi*hi; v_mfma_f32_16x16x32_bf16 with
+// FP32 accumulation), so the arithmetic is as accurate as the FP32 path while
+// the bf16 cores (16 times the FP32 rate) leave a 2.7x higher ceiling.
+//   * X is split once at job setup (logreg_split_kernel) into the two
+//     layouts the two contractions need, per 32-row chunk: row-major pieces
+//     (eta contracts over d) and d-major pieces (X^T r contracts over rows).
+//     A chunk (384 Dp bytes) is loaded once per block (coalesced 16-byte
+//     loads into registers, written to a double-buffered LDS image after the
+//     chunk in flight is done) and shared by the eight waves.
+//   * Theta is split in-kernel: each wave keeps the pieces of its two eta
+//     chain tiles in registers for the whole slice.
+//   1. eta (32 rows x 128 chains): wave w owns rows 16 (w & 1) .. +15 and
+//      chains 32 (w >> 1) .. +31; K = D rounded up to 32;
+//   2. r = y - sigmoid(eta), split, into LDS (chain-major pieces), and the
+//      log-likelihood with one log per four rows;
+//   3. X_chunk^T r (16 d x 16 chain tiles, K = the chunk's 32 rows): wave w
+//      owns chains 32 (w & 3) .. +31 and every other d tile from w >> 2, so
+//      each d tile's pieces serve two chain tiles and partial gradients need
+//      no cross-wave reduction.
+// LDS rows are padded so that the 16-byte operand reads of 8 consecutive
+// lanes fall in distinct banks.  Row slices are added in slice order (by the
+// NUTS transition that consumes the gradient, or by logreg_reduce_kernel for
+// the starting points); no float atomics, so every result is reproducible bit
+// for bit.  The grouped multi-job path (batch.hip) keeps the FP32 MFMA tile of
+// logreg_device.h.
 #include "logreg_device.h"
 
 namespace fsmmc {
 
 template <int DT, int NK8>
-__global__ __launch_bounds__(256) void logreg_grad_kernel(GradK a)
+__global__ __launch_bounds__(512) void logreg_grad_bf16_kernel(GradK a)
 {
-    logreg_grad_tile<DT, NK8>(a, blockIdx.x, blockIdx.y);
+    extern __shared__ __align__(16) unsigned char lds[];
+    logreg_grad_tile<DT, NK8>(a, blockIdx.x, blockIdx.y, lds);
 }
+
+// X (Np x Dp FP32) -> three bf16 pieces in the two chunk layouts the kernel
+// above loads: per 32-row chunk, [p][row][d] then [p][d][row].
+template <int DP>
+__global__ void logreg_split_kernel(const float* X, int Np, uint16_t* Xb)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)Np * DP) return;
+    const int row = (int)(i / DP), d = (int)(i % DP);
+    uint32_t pc[3];
+    split_bf16x3(X[i], pc[0], pc[1], pc[2]);
+    uint16_t* base = Xb + (size_t)(row / 32) * (192 * DP);
+    const int r = row % 32;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        base[p * 32 * DP + r * DP + d] = (uint16_t)pc[p];
+        base[96 * DP + p * DP * 32 + d * 32 + r] = (uint16_t)pc[p];
+    }
+}
+
 
 template <int EPL>
 __global__ __launch_bounds__(256) void logreg_reduce_kernel(ReduceK a)
@@ -36,15 +70,21 @@ __global__ __launch_bounds__(256) void logreg_reduce_kernel(ReduceK a)
     logreg_reduce_one<EPL>(a, (int)(blockIdx.x * 4 + (threadIdx.x >> 6)), threadIdx.x & 63);
 }
 
-// Gout == nullptr: leave the row-slice partials for the consumer to add.
-static hipError_t grad_launch(const JobDev& j, int dense, float* Gout, float* Uout, int gstride, hipStream_t s)
+template <int DT, int NK8>
+static hipError_t grad_bf16_launch(const GradK& g, int m, int nslices, hipStream_t s, bool setup)
 {
-    const GradK g = grad_view(j, dense);
-    const dim3 grid((j.m + 63) / 64, j.nslices), block(256);
-#define FSMMC_GRAD_CASE(K)                                                               \
-    case K:                                                                              \
-        hipLaunchKernelGGL((logreg_grad_kernel<(K) <= 8 ? 2 : 4, K>), grid, block, 0, s, g); \
-        break;
+    const void* f = (const void*)logreg_grad_bf16_kernel<DT, NK8>;
+    if (setup) return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, GradB<DT>::LDS);
+    hipLaunchKernelGGL((logreg_grad_bf16_kernel<DT, NK8>), dim3((m + 127) / 128, nslices), dim3(512),
+                       GradB<DT>::LDS, s, g);
+    return hipGetLastError();
+}
+
+// setup: only raise the kernel's dynamic LDS limit (once per job).
+static hipError_t grad_dispatch(const JobDev& j, const GradK& g, hipStream_t s, bool setup)
+{
+#define FSMMC_GRAD_CASE(K) \
+    case K: return grad_bf16_launch<(K) <= 8 ? 2 : 4, K>(g, j.m, j.nslices, s, setup);
     switch ((j.D + 7) / 8) {
         FSMMC_GRAD_CASE(1) FSMMC_GRAD_CASE(2) FSMMC_GRAD_CASE(3) FSMMC_GRAD_CASE(4)
         FSMMC_GRAD_CASE(5) FSMMC_GRAD_CASE(6) FSMMC_GRAD_CASE(7) FSMMC_GRAD_CASE(8)
@@ -53,7 +93,13 @@ static hipError_t grad_launch(const JobDev& j, int dense, float* Gout, float* Uo
     default: return hipErrorInvalidValue;
     }
 #undef FSMMC_GRAD_CASE
-    hipError_t e = hipGetLastError();
+}
+
+// Gout == nullptr: leave the row-slice partials for the consumer to add.
+static hipError_t grad_launch(const JobDev& j, int dense, float* Gout, float* Uout, int gstride, hipStream_t s)
+{
+    const GradK g = grad_view(j, dense);
+    hipError_t e = grad_dispatch(j, g, s, false);
     if (e != hipSuccess || !Gout) return e;
     const ReduceK r = reduce_view(j, dense, Gout, Uout, gstride);
     const dim3 rg((j.m + 3) / 4);
@@ -62,6 +108,25 @@ static hipError_t grad_launch(const JobDev& j, int dense, float* Gout, float* Uo
     else
         hipLaunchKernelGGL(logreg_reduce_kernel<2>, rg, dim3(256), 0, s, r);
     return hipGetLastError();
+}
+
+size_t logreg_split_bytes(const JobDev& j) { return (size_t)j.Np / 32 * 384 * j.Dp; }
+
+// Split X into the gradient kernel's bf16 pieces (after X is in place) and
+// allow the kernel its LDS.
+hipError_t logreg_setup(const JobDev& j, hipStream_t s)
+{
+    const size_t tot = (size_t)j.Np * j.Dp;
+    const dim3 grid((unsigned)((tot + 255) / 256));
+    if (j.Dp == 64)
+        hipLaunchKernelGGL(logreg_split_kernel<64>, grid, dim3(256), 0, s, (const float*)j.X, j.Np, (uint16_t*)j.Xb);
+    else if (j.Dp == 128)
+        hipLaunchKernelGGL(logreg_split_kernel<128>, grid, dim3(256), 0, s, (const float*)j.X, j.Np, (uint16_t*)j.Xb);
+    else
+        return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return grad_dispatch(j, grad_view(j, 0), s, true);
 }
 
 hipError_t nuts_gradient(const JobDev& j, hipStream_t s)

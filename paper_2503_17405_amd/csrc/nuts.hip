@@ -14,9 +14,10 @@
 //      amortized step").
 //   2. nuts_compact_kernel: list of chains that asked for a gradient, in
 //      chain order.
-//   3. logreg_grad_kernel: eta = X Theta, r = y - sigmoid(eta), X^T r and
-//      the log-likelihood, fused on FP32 MFMA for a tile of 64 listed chains
-//      and a slice of rows; eta never leaves registers.
+//   3. logreg_grad_bf16_kernel: eta = X Theta, r = y - sigmoid(eta), X^T r
+//      and the log-likelihood, fused for a tile of 128 listed chains and a
+//      slice of rows on the bf16 matrix cores (exact three-piece splits of
+//      the FP32 operands, FP32 results); eta never leaves registers.
 // The synchronized runtime uses the same kernels; a chain that finishes a
 // draw waits until every chain has finished it (device-side barrier), and in
 // vmap mode the gradient phase then covers every chain.
