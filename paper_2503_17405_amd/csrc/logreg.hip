@@ -27,8 +27,8 @@
 //      owns chains 32 (w & 3) .. +31 and every other d tile from w >> 2, so
 //      each d tile's pieces serve two chain tiles and partial gradients need
 //      no cross-wave reduction.
-// LDS rows are padded so that the 16-byte operand reads of 8 consecutive
-// lanes fall in distinct banks.  Row slices are added in slice order (by the
+// The LDS images are unpadded with XOR-permuted 16-byte units, so operand
+// reads and r writes are free of bank conflicts.  Row slices are added in slice order (by the
 // NUTS transition that consumes the gradient, or by logreg_reduce_kernel for
 // the starting points); no float atomics, so every result is reproducible bit
 // for bit.  The grouped multi-job path (batch.hip) keeps the FP32 MFMA tile of

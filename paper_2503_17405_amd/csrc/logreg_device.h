@@ -23,37 +23,33 @@ struct GradK {
     float* Upart;  // nslices x m
 };
 
+// LDS images of X chunks and of r, unpadded, with 16-byte units permuted
+// (XOR swizzles) so that the operand reads (16-byte reads: four passes of 16
+// lanes, lanes 0-7 with 16-23, 8-15 with 24-31, ...) touch 64 distinct banks
+// per pass.
 template <int DT>
 struct GradB {
-    static constexpr int DP = 32 * DT;          // padded dimension
-    static constexpr int PR = 2 * DP + 16;      // LDS bytes per row of a row-major piece
-    static constexpr int PD = 80;               // LDS bytes per column of a d-major piece (32 rows + pad)
-    static constexpr int XR = 3 * 32 * PR;      // row-major pieces of one chunk
-    static constexpr int XBUF = XR + 3 * DP * PD;  // + d-major pieces
-    static constexpr int RS = 3 * 128 * PD;     // r pieces, chain-major
-    static constexpr int LDS = 2 * XBUF + RS + 8 * 32 * 4 + 128 * 4;
-    static constexpr int CHUNK = 384 * DP;      // HBM bytes of one 32-row chunk (both layouts)
-    static constexpr int NV = CHUNK / 16 / 512; // 16-byte loads per thread per chunk
-    static_assert(CHUNK % (16 * 512) == 0, "chunk loads do not tile the block");
-    static_assert(128 * (DP + 4) * 4 <= 2 * XBUF, "gradient staging exceeds the X buffers");
-};
-
-// LDS byte offset of the 16-byte unit f of a chunk (HBM order: row-major
-// pieces [p][row][d], then d-major pieces [p][d][row]).
-template <int DT>
-__device__ __forceinline__ int gradb_lds_off(int f)
-{
-    using S = GradB<DT>;
-    constexpr int DP = S::DP;
-    if (f < 12 * DP) {
-        const int p = f / (4 * DP), r = f - p * 4 * DP;
-        const int row = r / (DP / 8), c = r - row * (DP / 8);
-        return p * 32 * S::PR + row * S::PR + 16 * c;
+    static constexpr int DP = 32 * DT;      // padded dimension
+    static constexpr int PR = 2 * DP;       // LDS bytes per row of a row-major piece
+    static constexpr int XRB = 3 * 32 * PR; // row-major pieces of one chunk
+    static constexpr int XDB = 3 * DP * 64; // d-major pieces of one chunk (64 bytes = 32 rows per column)
+    static constexpr int RSB = 3 * 128 * 64; // r pieces of one chunk, chain-major
+    static constexpr int XD0 = 2 * XRB, RS0 = XD0 + 2 * XDB, AUX0 = RS0 + 2 * RSB;
+    static constexpr int LDS = AUX0 + 8 * 32 * 4 + 128 * 4;
+    static constexpr int CHUNK = 384 * DP;  // HBM bytes of one 32-row chunk: row-major pieces, then d-major
+    static constexpr int NU = XRB / 16;     // 16-byte units per layout per chunk
+    static constexpr int NVH = (NU + 511) / 512;  // of which one thread of the block moves (at most)
+    static_assert(XRB == XDB && NVH <= 3, "chunk layouts");
+    static_assert(128 * (DP + 4) * 4 <= AUX0, "gradient staging exceeds the buffers");
+    // unit permutation of a row-major row: rows 8k .. 8k+7 map the eight lanes
+    // of a read pass to eight distinct unit pairs
+    static __device__ __forceinline__ int rowswz(int row)
+    {
+        return DT == 4 ? 2 * (4 * (row & 1) + ((row >> 1) & 3)) : 2 * ((row >> 1) & 3);
     }
-    const int g = f - 12 * DP;
-    const int p = g / (4 * DP), r = g - p * 4 * DP;
-    return S::XR + p * DP * S::PD + (r >> 2) * S::PD + 16 * (r & 3);
-}
+    // unit permutation of a 64-byte column (d-major X, r)
+    static __device__ __forceinline__ int colswz(int col) { return (col >> 1) & 3; }
+};
 
 __device__ __forceinline__ uint4 pack_bf16x8(const uint32_t (&v)[8])
 {
@@ -82,19 +78,24 @@ __device__ __forceinline__ floatx4 mfma_bf16x6(const uint4 (&A)[3], const uint4 
 // up to 8 is 8 NK8 (compile-time trip counts); NK8 = 0: any dimension up to
 // 32 DT (run-time trip counts over the same unrolled steps, so both forms
 // give the same bits).
+//
+// Software pipeline over the slice's 32-row chunks, one barrier per chunk:
+// pass i computes eta of chunk i + 1 (and its r, into the other r buffer)
+// and X^T r of chunk i, while the row-major half of chunk i + 2 and the
+// d-major half of chunk i + 1 stream into the idle X buffers, so the
+// sigmoid's vector work and the loads overlap the matrix-core work.
 template <int DT, int NK8 = 0>
 __device__ __forceinline__ void logreg_grad_tile(const GradK& a, int ct, int sl, unsigned char* lds)
 {
     using S = GradB<DT>;
-    constexpr int DP = S::DP, PR = S::PR, PD = S::PD;
+    constexpr int DP = S::DP, PR = S::PR;
+    constexpr float kLn2 = 0.693147180559945309f;
     constexpr int NK32 = NK8 > 0 ? (NK8 + 3) / 4 : DT;  // eta k steps of 32 (d), at most
     constexpr int NT = NK8 > 0 ? (NK8 + 1) / 2 : 2 * DT;  // gradient d tiles of 16 that can be nonzero
-    constexpr int NTW = (NT + 1) / 2;                   // d tiles per wave (at most)
     static_assert(NK8 >= 0 && 32 * NK32 <= DP, "dimension class exceeds the tile");
     const int nk32 = NK8 > 0 ? NK32 : (a.D + 31) >> 5;
     const int nt = NK8 > 0 ? NT : (a.D + 15) >> 4;
-    unsigned char* Rs = lds + 2 * S::XBUF;
-    float* Ured = reinterpret_cast<float*>(Rs + S::RS);  // [wave][32 chains]
+    float* Ured = reinterpret_cast<float*>(lds + S::AUX0);  // [wave][32 chains]
     int* cols = reinterpret_cast<int*>(Ured + 8 * 32);
 
     const int ncols = a.dense > 0 ? a.dense : *a.count;
@@ -108,32 +109,56 @@ __device__ __forceinline__ void logreg_grad_tile(const GradK& a, int ct, int sl,
     const int rb = sl * a.slice_rows;
     const int re = min(rb + a.slice_rows, a.N);
     const int nchunk = (re - rb + 31) / 32;
-    const uint4* xsrc = reinterpret_cast<const uint4*>(a.Xb) + (size_t)(rb / 32) * (S::CHUNK / 16);
-    // a chunk's share of this thread (named registers: an array here ends up in scratch)
-    static_assert(S::NV == 3 || S::NV == 6, "chunk share");
-    uint4 s0, s1, s2, s3, s4, s5;
-    auto load_chunk = [&](const uint4* src) {
-        s0 = src[tid];
-        s1 = src[tid + 512];
-        s2 = src[tid + 1024];
-        if (S::NV == 6) {
-            s3 = src[tid + 1536];
-            s4 = src[tid + 2048];
-            s5 = src[tid + 2560];
-        }
+    const unsigned char* xsrc = reinterpret_cast<const unsigned char*>(a.Xb) + (size_t)(rb / 32) * S::CHUNK;
+
+    // One layout of a chunk moves HBM -> registers (coalesced 16-byte loads,
+    // issued at the top of a pass) -> LDS (at its end).  LDS unit L of the
+    // row-major image holds (piece, row, unit L ^ rowswz(row)) of the chunk;
+    // of the d-major image, (piece, d, unit L ^ colswz(d)).  Named registers:
+    // an array here ends up in scratch.
+    auto rows_off = [&](int f) {
+        const int row = (f / (DP / 8)) & 31, u = f % (DP / 8);
+        return 16 * (f - u + (u ^ S::rowswz(row)));
     };
-    auto store_chunk = [&](unsigned char* dst) {
-        *reinterpret_cast<uint4*>(dst + gradb_lds_off<DT>(tid)) = s0;
-        *reinterpret_cast<uint4*>(dst + gradb_lds_off<DT>(tid + 512)) = s1;
-        *reinterpret_cast<uint4*>(dst + gradb_lds_off<DT>(tid + 1024)) = s2;
-        if (S::NV == 6) {
-            *reinterpret_cast<uint4*>(dst + gradb_lds_off<DT>(tid + 1536)) = s3;
-            *reinterpret_cast<uint4*>(dst + gradb_lds_off<DT>(tid + 2048)) = s4;
-            *reinterpret_cast<uint4*>(dst + gradb_lds_off<DT>(tid + 2560)) = s5;
-        }
+    auto cols_off = [&](int f) {
+        const int d = (f >> 2) & (DP - 1), u = f & 3;
+        return 16 * (f - u + (u ^ S::colswz(d)));
     };
-    if (nchunk > 0) load_chunk(xsrc);
-    __syncthreads();  // cols
+    // this thread's units of each layout: f = tid, tid + 512, tid + 1024 (when < NU)
+    const bool has1 = S::NVH > 1 && tid + 512 < S::NU, has2 = S::NVH > 2 && tid + 1024 < S::NU;
+    const int ro0 = rows_off(tid), ro1 = rows_off(tid + 512), ro2 = rows_off(tid + 1024);
+    const int co0 = cols_off(tid), co1 = cols_off(tid + 512), co2 = cols_off(tid + 1024);
+    uint4 sr0, sr1, sr2;  // row-major half in flight
+    auto stage_rows = [&](const unsigned char* src) {
+        const uint4* s4 = reinterpret_cast<const uint4*>(src);
+        sr0 = s4[tid];
+        if (has1) sr1 = s4[tid + 512];
+        if (has2) sr2 = s4[tid + 1024];
+    };
+    auto store_rows = [&](unsigned char* dst) {
+        *reinterpret_cast<uint4*>(dst + ro0) = sr0;
+        if (has1) *reinterpret_cast<uint4*>(dst + ro1) = sr1;
+        if (has2) *reinterpret_cast<uint4*>(dst + ro2) = sr2;
+    };
+    uint4 sd0, sd1, sd2;  // d-major half in flight
+    auto stage_cols = [&](const unsigned char* src) {
+        const uint4* s4 = reinterpret_cast<const uint4*>(src);
+        sd0 = s4[tid];
+        if (has1) sd1 = s4[tid + 512];
+        if (has2) sd2 = s4[tid + 1024];
+    };
+    auto store_cols = [&](unsigned char* dst) {
+        *reinterpret_cast<uint4*>(dst + co0) = sd0;
+        if (has1) *reinterpret_cast<uint4*>(dst + co1) = sd1;
+        if (has2) *reinterpret_cast<uint4*>(dst + co2) = sd2;
+    };
+    auto rows_src = [&](int c) { return xsrc + (size_t)c * S::CHUNK; };
+    auto cols_src = [&](int c) { return xsrc + (size_t)c * S::CHUNK + S::XRB; };
+    if (nchunk > 0) {
+        stage_rows(rows_src(0));
+        store_rows(lds);
+    }
+    __syncthreads();  // cols, and the row-major half of chunk 0
 
     // eta roles and the Theta pieces of this wave's two chain tiles (B operand:
     // lane holds Theta[chain 16 t + l16][32 kk + 8 q4 .. + 7])
@@ -159,98 +184,166 @@ __device__ __forceinline__ void logreg_grad_tile(const GradK& a, int ct, int sl,
             thb[t][kk][2] = pack_bf16x8(l);
         }
     }
-    if (nchunk > 0) store_chunk(lds);
 
-    // gradient roles: chain tiles 2 cp, 2 cp + 1; d tiles h, h + 2, ...
-    const int cp = wave & 3, hh = wave >> 2;
-    floatx4 accg[NTW][2];
+    // gradient roles: chain tile `wave` (chains 16 wave .. + 15), every d tile
+    floatx4 accg[NT];
 #pragma unroll
-    for (int j = 0; j < NTW; ++j)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) accg[j][u][q] = 0.0f;
+        for (int q = 0; q < 4; ++q) accg[t][q] = 0.0f;
     float uacc[2] = {0.0f, 0.0f};
 
-    for (int ch = 0; ch < nchunk; ++ch) {
-        const int buf = ch & 1;
-        // the next chunk (the last chunk again on the last pass: its copy into
-        // the idle buffer is never read)
-        load_chunk(xsrc + (size_t)min(ch + 1, nchunk - 1) * (S::CHUNK / 16));
-        __syncthreads();  // chunk ch in buffer buf; the previous chunk's r and buffer buf ^ 1 no longer read
-        const unsigned char* XB = lds + buf * S::XBUF;
-        // 1. eta: A = X rows (lane: row 16 rt + l16, d 32 kk + 8 q4 .. + 7), B = Theta pieces
-        floatx4 e0 = {0.0f, 0.0f, 0.0f, 0.0f}, e1 = e0;
-        const unsigned char* xr = XB + (16 * rt + l16) * PR + 16 * q4;
+    // 1. eta of chunk c (32 rows x 128 chains): A = X rows (lane: row 16 rt + l16,
+    //    d 32 kk + 8 q4 .. + 7), B = Theta pieces
+    const int xsw = S::rowswz(16 * rt + l16);
+    auto eta = [&](int c, floatx4& e0, floatx4& e1) {
+        const unsigned char* xr = lds + (c & 1) * S::XRB + (16 * rt + l16) * PR;
+        e0 = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        e1 = e0;
 #pragma unroll
         for (int kk = 0; kk < NK32; ++kk) {
             if (kk >= nk32) break;
-            const uint4 xa[3] = {*reinterpret_cast<const uint4*>(xr + 64 * kk),
-                                 *reinterpret_cast<const uint4*>(xr + 32 * PR + 64 * kk),
-                                 *reinterpret_cast<const uint4*>(xr + 64 * PR + 64 * kk)};
+            const int o = 16 * ((4 * kk + q4) ^ xsw);
+            const uint4 xa[3] = {*reinterpret_cast<const uint4*>(xr + o),
+                                 *reinterpret_cast<const uint4*>(xr + 32 * PR + o),
+                                 *reinterpret_cast<const uint4*>(xr + 64 * PR + o)};
             e0 = mfma_bf16x6(xa, thb[0][kk], e0);
             e1 = mfma_bf16x6(xa, thb[1][kk], e1);
         }
-        // 2. r = y - sigmoid(eta), split into pieces, to LDS; log-likelihood:
-        //    sum [y eta - max(eta, 0)] minus one log of the product of the four
-        //    factors 1 + e^-|eta| (each in (1, 2])
-        const int r0 = rb + 32 * ch;
+    };
+    // 2. r = y - sigmoid(eta) of chunk c, split into pieces, into r buffer c & 1;
+    //    log-likelihood: sum [y eta - max(eta, 0)] minus one log of the product
+    //    of the four factors 1 + e^-|eta| (each in (1, 2], so the product is a
+    //    normal number in [1, 16] and the hardware log2 is accurate).  Rows
+    //    past the data are zero rows of X and y, so eta = 0 there: they leave
+    //    the gradient and the linear term unchanged, and their factor 2 is
+    //    taken back (ln 2 each) once at the end of the slice.
+    //    Value j: column tile j / 4, row j % 4 of the lane's four.
+    struct Resid {
+        float r[8];
+        float lin[2], prod[2];
+    };
+    auto resid_value = [&](int j, const floatx4& e0, const floatx4& e1, const float4& yv4, Resid& R) {
+        const int i = j & 3, t = j >> 2;
+        const float v = t ? e1[i] : e0[i];
+        const float yv = i == 0 ? yv4.x : i == 1 ? yv4.y : i == 2 ? yv4.z : yv4.w;
+        const bool pos = v >= 0.0f;
+        const float ex = __expf(-fabsf(v));
+        const float inv = __builtin_amdgcn_rcpf(1.0f + ex);  // hardware reciprocal, 1 ulp
+        const float sig = pos ? inv : ex * inv;
+        R.lin[t] = fmaf(pos ? yv - 1.0f : yv, v, R.lin[t]);  // y v - max(v, 0)
+        R.prod[t] *= 1.0f + ex;
+        R.r[j] = yv - sig;
+    };
+    auto resid_finish = [&](int c, Resid& R) {
+        unsigned char* Rs = lds + S::RS0 + (c & 1) * S::RSB;
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-            const floatx4 e = t ? e1 : e0;
-            const int col = 32 * ep + 16 * t + l16;
-            float lin = 0.0f, prod = 1.0f;
+            uacc[t] += R.lin[t] - kLn2 * __builtin_amdgcn_logf(R.prod[t]);  // hardware log2
             uint32_t ph[4], pm[4], pl[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int row = r0 + 16 * rt + 4 * q4 + i;
-                const bool ok = row < re;
-                const float v = e[i];
-                const float yv = a.y[row];
-                const float ex = __expf(-fabsf(v));
-                const float inv = __builtin_amdgcn_rcpf(1.0f + ex);  // hardware reciprocal, 1 ulp
-                const float sig = v >= 0.0f ? inv : ex * inv;
-                lin += ok ? (yv * v - fmaxf(v, 0.0f)) : 0.0f;
-                prod *= ok ? 1.0f + ex : 1.0f;
-                split_bf16x3(ok ? (yv - sig) : 0.0f, ph[i], pm[i], pl[i]);
-            }
-            uacc[t] += lin - __logf(prod);
-            unsigned char* rp = Rs + col * PD + 2 * (16 * rt + 4 * q4);
+            for (int i = 0; i < 4; ++i) split_bf16x3(R.r[4 * t + i], ph[i], pm[i], pl[i]);
+            // rows 16 rt + 4 q4 .. + 3: 8 bytes in unit 2 rt + q4 / 2 of the column
+            const int col = 32 * ep + 16 * t + l16;
+            unsigned char* rp = Rs + col * 64 + 16 * ((2 * rt + (q4 >> 1)) ^ S::colswz(col)) + 8 * (q4 & 1);
             *reinterpret_cast<uint2*>(rp) = make_uint2(ph[0] | (ph[1] << 16), ph[2] | (ph[3] << 16));
-            *reinterpret_cast<uint2*>(rp + 128 * PD) = make_uint2(pm[0] | (pm[1] << 16), pm[2] | (pm[3] << 16));
-            *reinterpret_cast<uint2*>(rp + 256 * PD) = make_uint2(pl[0] | (pl[1] << 16), pl[2] | (pl[3] << 16));
+            *reinterpret_cast<uint2*>(rp + 128 * 64) = make_uint2(pm[0] | (pm[1] << 16), pm[2] | (pm[3] << 16));
+            *reinterpret_cast<uint2*>(rp + 256 * 64) = make_uint2(pl[0] | (pl[1] << 16), pl[2] | (pl[3] << 16));
         }
-        __syncthreads();  // r complete
-        // 3. X_chunk^T r: A = X columns (lane: d 16 t + l16, rows 8 q4 .. + 7), B = r pieces
-        uint4 rpc[2][3];
+    };
+    auto resid = [&](int c, const floatx4& e0, const floatx4& e1, const float4& yv4) {
+        Resid R = {{}, {0.0f, 0.0f}, {1.0f, 1.0f}};
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const unsigned char* rp = Rs + (32 * cp + 16 * u + l16) * PD + 16 * q4;
+        for (int j = 0; j < 8; ++j) resid_value(j, e0, e1, yv4, R);
+        resid_finish(c, R);
+    };
+    // 3. X^T r of chunk c: A = X columns (lane: d 16 t + l16, rows 8 q4 .. + 7),
+    //    B = r pieces.  Fused form: the residual values of chunk cr ride
+    //    between the d tiles' MFMAs (one per tile, fenced so that the
+    //    scheduler keeps them there and the vector work overlaps the matrix
+    //    cores); cr < 0: none.
+    const int csw = 16 * (q4 ^ S::colswz(l16));  // this lane's unit in a 64-byte column
+    auto xtr_resid = [&](int c, int cr, const floatx4& e0, const floatx4& e1, const float4& yv4) {
+        const unsigned char* Rs = lds + S::RS0 + (c & 1) * S::RSB;
+        uint4 rpc[3];
+        const unsigned char* rp = Rs + (16 * wave + l16) * 64 + csw;
 #pragma unroll
-            for (int p = 0; p < 3; ++p) rpc[u][p] = *reinterpret_cast<const uint4*>(rp + p * 128 * PD);
+        for (int p = 0; p < 3; ++p) rpc[p] = *reinterpret_cast<const uint4*>(rp + p * 128 * 64);
+        const unsigned char* XD = lds + S::XD0 + (c & 1) * S::XDB + l16 * 64 + csw;
+        Resid R = {{}, {0.0f, 0.0f}, {1.0f, 1.0f}};
+        // d tile t's pieces are read one group ahead of its MFMAs
+        auto ld = [&](int t, uint4 (&x)[3]) {
+            const unsigned char* xp = XD + 16 * t * 64;
+            x[0] = *reinterpret_cast<const uint4*>(xp);
+            x[1] = *reinterpret_cast<const uint4*>(xp + DP * 64);
+            x[2] = *reinterpret_cast<const uint4*>(xp + 2 * DP * 64);
+        };
+        uint4 xb[2][3];  // ping-pong by tile parity (static indices once unrolled)
+        ld(0, xb[0]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            if (t + 1 < NT && t + 1 < nt) ld(t + 1, xb[(t + 1) & 1]);
+            if (t < nt) accg[t] = mfma_bf16x6(xb[t & 1], rpc, accg[t]);
+            if (cr >= 0 && t < 8) resid_value(t, e0, e1, yv4, R);
+            __builtin_amdgcn_sched_barrier(0);
         }
-        const unsigned char* XD = XB + S::XR;
+        if (cr >= 0) {
 #pragma unroll
-        for (int j = 0; j < NTW; ++j) {
-            const int t = hh + 2 * j;
-            if (t < nt) {
-                const unsigned char* xp = XD + (16 * t + l16) * PD + 16 * q4;
-                const uint4 xa[3] = {*reinterpret_cast<const uint4*>(xp),
-                                     *reinterpret_cast<const uint4*>(xp + DP * PD),
-                                     *reinterpret_cast<const uint4*>(xp + 2 * DP * PD)};
-                accg[j][0] = mfma_bf16x6(xa, rpc[0], accg[j][0]);
-                accg[j][1] = mfma_bf16x6(xa, rpc[1], accg[j][1]);
-            }
+            for (int j = NT; j < 8; ++j) resid_value(j, e0, e1, yv4, R);
+            resid_finish(cr, R);
         }
-        store_chunk(lds + (buf ^ 1) * S::XBUF);
+    };
+    // y of this lane's four rows of chunk c (16-byte aligned; rows past the
+    // data are read from the zero padding and masked)
+    auto yload = [&](int c) {
+        return *reinterpret_cast<const float4*>(a.y + rb + 32 * c + 16 * rt + 4 * q4);
+    };
+
+    // Pass c (c = -1 .. nchunk - 2) reads the row-major half of chunk c + 1,
+    // the d-major half of chunk c and r of chunk c, all in place since the
+    // barrier that ended pass c - 1, and fills buffers whose readers finished
+    // before that barrier: the row-major half of chunk c + 2 goes where chunk
+    // c's was, the d-major half of c + 1 where c - 1's was, r of c + 1 where
+    // r of c - 1 was.
+    if (nchunk > 0) {
+        stage_cols(cols_src(0));
+        if (nchunk > 1) stage_rows(rows_src(1));
+        floatx4 e0, e1;
+        eta(0, e0, e1);
+        resid(0, e0, e1, yload(0));
+        float4 yv = yload(min(1, nchunk - 1));  // y one pass ahead: in registers when the pass starts
+        store_cols(lds + S::XD0);
+        if (nchunk > 1) store_rows(lds + S::XRB);
+        __syncthreads();
+        for (int c = 0; c + 1 < nchunk; ++c) {
+            const bool more = c + 2 < nchunk;
+            if (more) stage_rows(rows_src(c + 2));
+            stage_cols(cols_src(c + 1));
+            const float4 ycur = yv;
+            yv = yload(min(c + 2, nchunk - 1));
+            eta(c + 1, e0, e1);
+            xtr_resid(c, c + 1, e0, e1, ycur);
+            if (more) store_rows(lds + (c & 1) * S::XRB);
+            store_cols(lds + S::XD0 + ((c + 1) & 1) * S::XDB);
+            __syncthreads();
+        }
+        xtr_resid(nchunk - 1, -1, e0, e1, yv);
     }
-    // log-likelihood per chain: lanes of one column hold different rows
+    // log-likelihood per chain: take back ln 2 per padding row of this lane
+    // (only the slice's last chunk can hold any), then add up the lanes of one
+    // column (they hold different rows)
+    if (nchunk > 0) {
+        const int rowl = rb + 32 * (nchunk - 1) + 16 * rt + 4 * q4;
+        const float npad = (float)(min(4, max(0, rowl + 4 - re)));
+        uacc[0] += npad * kLn2;
+        uacc[1] += npad * kLn2;
+    }
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         uacc[t] += __shfl_xor(uacc[t], 16, 64);
         uacc[t] += __shfl_xor(uacc[t], 32, 64);
     }
-    __syncthreads();  // X buffers free
+    __syncthreads();  // X and r buffers free
     if (q4 == 0) {
         Ured[wave * 32 + l16] = uacc[0];
         Ured[wave * 32 + 16 + l16] = uacc[1];
@@ -259,14 +352,10 @@ __device__ __forceinline__ void logreg_grad_tile(const GradK& a, int ct, int sl,
     constexpr int TP = DP + 4;
     float* Red = reinterpret_cast<float*>(lds);
 #pragma unroll
-    for (int j = 0; j < NTW; ++j) {
-        const int t = hh + 2 * j;
+    for (int t = 0; t < NT; ++t) {
         if (t < nt) {
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    Red[(32 * cp + 16 * u + l16) * TP + 16 * t + 4 * q4 + q] = accg[j][u][q];
+            for (int q = 0; q < 4; ++q) Red[(16 * wave + l16) * TP + 16 * t + 4 * q4 + q] = accg[t][q];
         }
     }
     const int DZ = DP - 16 * nt;  // d past the last tile: zero
