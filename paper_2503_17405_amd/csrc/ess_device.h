@@ -385,7 +385,8 @@ __device__ __forceinline__ void nu_gemm_block(const NuK<float>& a, int col0)
 //   logistic:  sum y f - softplus(f), softplus(f) = max(f, 0) + log(1 + e^-|f|).
 // FP32 logistic takes the log of the product of the factors 1 + e^-|f|: each
 // lies in (1, 2], so the product of at most 16 cannot overflow, and one log
-// replaces EPL of them (the transcendental units bound this loop).
+// replaces EPL of them (the vector units bound this loop, so it is written
+// for few instructions per element).
 // FULL: D == 64 EPL, every lane element exists and the masks drop out (the
 // same operations on the same values as the masked form).
 template <typename T, int EPL, bool FULL = false>
@@ -403,16 +404,20 @@ __device__ __forceinline__ T ess_lane_loglik(const T (&f)[EPL], const T (&yv)[EP
         return acc;
     }
     if constexpr (sizeof(T) == 4) {
+        // three running sums: y f (one FMA per element), max(f, 0) (one med3
+        // and one add) and the product of the factors (one FMA: p + p e^-|f|);
+        // the product lies in [1, 2^16], where the hardware log2 is accurate
         static_assert(EPL <= 16, "the factor product must stay below 2^16");
-        float prod = 1.0f;
+        float relu = 0.0f, prod = 1.0f;
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
             const bool in = FULL || e * 64 + lane < D;
-            const float lin = yv[e] * f[e] - fmaxf(f[e], 0.0f);
-            acc += in ? lin : 0.0f;
-            prod *= in ? 1.0f + __expf(-fabsf(f[e])) : 1.0f;
+            acc = fmaf(in ? yv[e] : 0.0f, f[e], acc);
+            const float r = in ? __builtin_amdgcn_fmed3f(f[e], 0.0f, 3.40282347e38f) : 0.0f;
+            relu = e == 0 ? r : relu + r;
+            prod = fmaf(prod, in ? __expf(-fabsf(f[e])) : 0.0f, prod);
         }
-        return acc - __logf(prod);
+        return acc - relu - 0.693147180559945309f * __builtin_amdgcn_logf(prod);
     } else {
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
