@@ -462,10 +462,13 @@ def bench_gphyper(F, ctx, args):
     from paper_2503_17405_amd import inputs
     res = dict(workload="ESS on GP-regression hyperparameters: n observations with 6 inputs (synthetic "
                         "stand-in for the 6-feature regression data), N(0,I) prior on (tau, lambda, sigma), "
-                        "FP64 Cholesky per likelihood, %d chains x %d draws" % (args.gph_chains, args.gph_draws),
+                        "FP64 Cholesky per likelihood, %d chains x %d draws (%d draws for n > 128, where "
+                        "a block of four waves factors each matrix)"
+                        % (args.gph_chains, args.gph_draws, args.gph_big_draws),
                runs={})
-    m, n = args.gph_chains, args.gph_draws
+    m = args.gph_chains
     for nobs in args.gph_obs:
+        n = args.gph_draws if nobs <= 128 else args.gph_big_draws
         w = inputs.gp_hyper(n=nobs, n_chains=m, seed=9001)
         tg = F.gp_hyper_target(torch.tensor(w["X"], device="cuda"), torch.tensor(w["y"], device="cuda"),
                                w["jitter"])
@@ -481,7 +484,7 @@ def bench_gphyper(F, ctx, args):
         st = job.stats()
         job.free()
         ref = checksum(out.view(torch.float32))
-        r = dict(obs=nobs, seconds=t_fsm, draws_per_s=m * n / t_fsm, likelihoods=st["steps"],
+        r = dict(obs=nobs, draws=n, seconds=t_fsm, draws_per_s=m * n / t_fsm, likelihoods=st["steps"],
                  likelihoods_per_s=st["steps"] / t_fsm, cholesky_flop_per_likelihood=nobs ** 3 / 3.0,
                  mean_loop=st["mean_loops"], mean_max_loop=st["mean_max_loops"], R_hat_m=st["r_hat"])
         sync = {}
@@ -747,7 +750,8 @@ def main():
     ap.add_argument("--slice-chains", type=int, nargs="+", default=[1024, 65536])
     ap.add_argument("--slice-draws", type=int, default=1000)
     ap.add_argument("--no-gph", action="store_true")
-    ap.add_argument("--gph-obs", type=int, nargs="+", default=[25, 100])
+    ap.add_argument("--gph-obs", type=int, nargs="+", default=[25, 100, 414])
+    ap.add_argument("--gph-big-draws", type=int, default=100)
     ap.add_argument("--gph-chains", type=int, default=1024)
     ap.add_argument("--gph-draws", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")

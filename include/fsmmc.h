@@ -95,7 +95,7 @@ typedef struct {
     int32_t kind;     /* fsmmc_target_kind                                         */
     int32_t dim;      /* d >= 1                                                    */
     int32_t n_data;   /* LOGREG: number of rows of X; MOG: components K in [1, 8];
-                         GP_HYPER: observations n in [1, 128]                     */
+                         GP_HYPER: observations n in [1, 512]                     */
     int32_t aux;      /* GP_HYPER: input dimension p in [1, 16]; otherwise 0       */
     const void* X;    /* LOGREG: n_data x dim design matrix; MOG: K x dim means mu_k;
                          GP_HYPER: n_data x aux inputs                            */

@@ -245,7 +245,7 @@ fsmmc_status fsmmc::validate_specs(const fsmmc_target_spec* t, const fsmmc_sampl
         if (t->dim != 3) return fail(FSMMC_EINVAL, "GP_HYPER has dim 3 (tau, lambda, sigma)");
         if (!t->X || !t->y) return fail(FSMMC_EINVAL, "GP_HYPER needs X and y");
         if (t->n_data < 1 || t->n_data > gph_max_obs())
-            return fail(FSMMC_ENOTSUP, "GP_HYPER needs 1 to 128 observations");
+            return fail(FSMMC_ENOTSUP, "GP_HYPER needs 1 to 512 observations");
         if (t->aux < 1 || t->aux > gph_max_inputs()) return fail(FSMMC_EINVAL, "GP_HYPER input dimension must be in [1, 16]");
         if (!(t->noise_sd >= 0.0) || !std::isfinite(t->noise_sd)) return fail(FSMMC_EINVAL, "jitter must be >= 0");
         return FSMMC_OK;
@@ -413,7 +413,7 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
     }
     d.tstop = (uint32_t)d.n;
 
-    if (d.kind == FSMMC_ESS && d.target == FSMMC_GP_HYPER) {  // wave per chain, FP64, in-wave Cholesky
+    if (d.kind == FSMMC_ESS && d.target == FSMMC_GP_HYPER) {  // FP64 Cholesky by a wave (n <= 128) or a block
         d.Dp = d.D;
         d.N = target->n_data;
         d.pdim = target->aux;
@@ -431,6 +431,7 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
         HIP_TRY_JOB(hipMemcpyAsync(d.X, target->X, (size_t)d.N * d.pdim * 8, hipMemcpyDeviceToDevice, job->stream));
         HIP_TRY_JOB(hipMemcpyAsync(d.y, target->y, (size_t)d.N * 8, hipMemcpyDeviceToDevice, job->stream));
         HIP_TRY_JOB(gph_setup(d));
+        if (gph_slot_bytes(d)) ALLOC(d.gslot, gph_slot_bytes(d));
         HIP_TRY_JOB(gph_init_state(d, x0, job->stream));
         job->launches += x0 ? 2 : 1;
     } else if (d.kind == FSMMC_ESS) {

@@ -36,6 +36,7 @@ struct JobDev {
     void* y = nullptr;  // Dp (GP) or Np (LOGREG) labels / observations
     void* X = nullptr;  // LOGREG: Np x Dp, zero padded
     void* Xb = nullptr; // LOGREG: X as three bf16 pieces, row- and d-major per 32-row chunk (logreg.hip)
+    void* gslot = nullptr;  // GP_HYPER with n > 128: a Cholesky work matrix per persistent block
     void* prec = nullptr;
 
     // common chain state
@@ -132,6 +133,7 @@ hipError_t mog_eval(const JobDev& j, int n, const float* pts, float* G, float* U
 // ESS on GP-regression hyperparameters (gph.hip); mode 0 FSM, 1 one synchronized
 // draw, 2 vmap padding of that draw
 int gph_max_obs();
+size_t gph_slot_bytes(const JobDev& j);  // after gph_setup
 int gph_max_inputs();
 hipError_t gph_setup(JobDev& j);
 hipError_t gph_init_state(const JobDev& j, const void* x0, hipStream_t s);

@@ -1,6 +1,7 @@
 """GPU parity of elliptical slice sampling on GP-regression hyperparameters
 (Sec. 7.2): an O(n^3) Cholesky of the n x n kernel matrix inside every loop
-iteration, computed in FP64 by the chain's wavefront.  FSM runtime ==
+iteration, computed in FP64 by the chain's wavefront (n <= 128) or by a
+block with a blocked factorisation (n > 128).  FSM runtime ==
 synchronized runtime (vmap and compact) bit for bit; draws match the FP64
 oracle per draw (1e-9 relative: both sides FP64, the factorisations add up
 in different orders)."""
@@ -48,9 +49,10 @@ def run(F, ctx, w, m, n, seed, runtime="fsm", max_steps=0, x0=None):
         job.free()
 
 
-def test_gphyper_runtimes_bit_exact(F, ctx):
-    w = inputs.gp_hyper(n=40, seed=11)
-    m, n, seed = 96, 30, 12
+@pytest.mark.parametrize("nobs,m,n", [(40, 96, 30), (300, 24, 6)])
+def test_gphyper_runtimes_bit_exact(F, ctx, nobs, m, n):
+    w = inputs.gp_hyper(n=nobs, seed=11)
+    seed = 12
     S0, C0, st0 = run(F, ctx, w, m, n, seed, runtime="vmap")
     for runtime, steps in [("fsm", 0), ("fsm", 3), ("compact", 0)]:
         S, C, st = run(F, ctx, w, m, n, seed, runtime, steps)
@@ -58,14 +60,17 @@ def test_gphyper_runtimes_bit_exact(F, ctx):
         assert st["steps"] == C.sum()
     assert st0["steps"] + st0["padded_steps"] == m * C0.max(axis=0).sum()
     assert st0["guard_trips"] == 0 and np.isfinite(S0).all()
-    print("GP hyper n=40: mean evaluations %.2f, mean max over %d chains %.1f, R %.2f"
-          % (C0.mean(), m, C0.max(axis=0).mean(), st0["r_hat"]))
+    print("GP hyper n=%d: mean evaluations %.2f, mean max over %d chains %.1f, R %.2f"
+          % (nobs, C0.mean(), m, C0.max(axis=0).mean(), st0["r_hat"]))
 
 
-@pytest.mark.parametrize("nobs", [1, 25, 100, 128])
+@pytest.mark.parametrize("nobs", [1, 25, 100, 128, 129, 250, 414])
 def test_gphyper_oracle_parity(F, ctx, nobs):
-    w = inputs.gp_hyper(n=nobs, n_chains=32, seed=20 + nobs)
-    m, n, seed = 32, 40 if nobs >= 100 else 100, 21 + nobs
+    # 129 .. 414: the block factorisation (a ragged last panel at 129, 250 and
+    # 414; 414 is the paper's data size)
+    m = 32 if nobs <= 128 else 8
+    w = inputs.gp_hyper(n=nobs, n_chains=m, seed=20 + nobs)
+    n, seed = (100 if nobs < 100 else 40 if nobs <= 128 else 12), 21 + nobs
     x0 = w["x0"]
     S, C, _ = run(F, ctx, w, m, n, seed, x0=x0)
     tg = O.gp_hyper_target(w["X"], w["y"], w["jitter"])
@@ -91,7 +96,7 @@ def test_gphyper_default_start(F, ctx):
 
 
 def test_gphyper_argument_errors(F, ctx):
-    w = inputs.gp_hyper(n=129, seed=1)
+    w = inputs.gp_hyper(n=513, seed=1)
     with pytest.raises(F.FsmmcError) as e:
         F.Job(ctx, target(F, w), F.ess_sampler(F.F64), 4, 4, 1)
     assert e.value.status == F.ENOTSUP
