@@ -208,6 +208,28 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // chain's last draw exits at once.  The directions are written with
 // nontemporal stores (they are read once, by the next window's kernel), which
 // keeps L's pieces in L2.
+// The four normals of a direction block with the hardware transcendentals
+// (log2, square root, and sine / cosine of 2 pi u, which the hardware takes
+// in revolutions): the same Philox words and Box-Muller pairs as normals4,
+// about 1e-6 absolute error per normal instead of the library functions'
+// correct rounding, for a fraction of the vector instructions.  Only the
+// large-D direction product uses them (its z generation competes with the
+// matrix cores for issue); every kernel that computes those directions calls
+// this function, so all runtimes see the same bits.
+__device__ __forceinline__ void normals4_hw(uint64_t seed, uint32_t chain, uint32_t draw, uint32_t role,
+                                            uint32_t b, float z[4])
+{
+    const Ctr4 w = stream_block(seed, chain, draw, role, 0, b);
+    const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const float u1 = u01<float>(wv[2 * p]), u2 = u01<float>(wv[2 * p + 1]);
+        const float r = __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u1));  // -2 ln u1
+        z[2 * p] = r * __builtin_amdgcn_cosf(u2);
+        z[2 * p + 1] = r * __builtin_amdgcn_sinf(u2);
+    }
+}
+
 template <int RT, int CT = 2>
 __device__ __forceinline__ void nu_gemm_block_bf16(const NuK<float>& a, int col0)
 {
@@ -240,7 +262,7 @@ __device__ __forceinline__ void nu_gemm_block_bf16(const NuK<float>& a, int col0
     auto draw_put = [&](int kc, int buf, int koff) {
         const int kb = kc + 4 * zb;
         float z[4];
-        normals4<float>(a.seed, (uint32_t)zchain, zdraw, a.role, 0, (uint32_t)(kb >> 2), z);
+        normals4_hw(a.seed, (uint32_t)zchain, zdraw, a.role, (uint32_t)(kb >> 2), z);
 #pragma unroll
         for (int i = 0; i < 4; i += 2) {
             uint32_t pc[2][3];
