@@ -14,25 +14,18 @@
 //   * X is split once at job setup (logreg_split_kernel) into the two
 //     layouts the two contractions need, per 32-row chunk: row-major pieces
 //     (eta contracts over d) and d-major pieces (X^T r contracts over rows).
-//     A chunk (384 Dp bytes) is loaded once per block (coalesced 16-byte
-//     loads into registers, written to a double-buffered LDS image after the
-//     chunk in flight is done) and shared by the eight waves.
-//   * Theta is split in-kernel: each wave keeps the pieces of its two eta
-//     chain tiles in registers for the whole slice.
-//   1. eta (32 rows x 128 chains): wave w owns rows 16 (w & 1) .. +15 and
-//      chains 32 (w >> 1) .. +31; K = D rounded up to 32;
-//   2. r = y - sigmoid(eta), split, into LDS (chain-major pieces), and the
-//      log-likelihood with one log per four rows;
-//   3. X_chunk^T r (16 d x 16 chain tiles, K = the chunk's 32 rows): wave w
-//      owns chains 32 (w & 3) .. +31 and every other d tile from w >> 2, so
-//      each d tile's pieces serve two chain tiles and partial gradients need
-//      no cross-wave reduction.
+//   * Waves 0-3 compute eta (Theta's pieces split in-kernel and kept in
+//     registers) and r = y - sigmoid(eta) with the log-likelihood; waves 4-7
+//     compute X_chunk^T r.  The two roles run one chunk apart in a software
+//     pipeline with one barrier per chunk, so the residuals' vector work
+//     overlaps the matrix-core work of the other waves on the same SIMD
+//     (logreg_grad_tile in logreg_device.h).
 // The LDS images are unpadded with XOR-permuted 16-byte units, so operand
-// reads and r writes are free of bank conflicts.  Row slices are added in slice order (by the
-// NUTS transition that consumes the gradient, or by logreg_reduce_kernel for
-// the starting points); no float atomics, so every result is reproducible bit
-// for bit.  The grouped multi-job path (batch.hip) keeps the FP32 MFMA tile of
-// logreg_device.h.
+// reads are free of bank conflicts.  Row slices are added in slice order (by
+// the NUTS transition that consumes the gradient, or by logreg_reduce_kernel
+// for the starting points); no float atomics, so every result is
+// reproducible bit for bit.  The grouped multi-job path (batch.hip) runs the
+// same device function.
 #include "logreg_device.h"
 
 namespace fsmmc {
