@@ -674,6 +674,10 @@ def bench_serve(F, args):
     return dict(workload="%d jobs, Poisson arrivals at 50 jobs/s; ESS GP-logistic D~U{64..1024} or NUTS "
                          "logistic regression D~U{10..100}, N~U{1000..10000}; m~U{16..1024}, "
                          "n~U{200..2000}; FP32" % len(stream),
+                prefix="the first %d jobs of the configured 2000-job stream (same generator and seed); "
+                       "the one-job-at-a-time leg of the whole stream would take about %.0f minutes at "
+                       "this prefix's rate" % (len(stream), t_done / len(stream) * 2000 / 60.0)
+                       if len(stream) < 2000 else None,
                 jobs=len(stream), draws=draws, host_prep_s=prep_s, all_ok=bool(ok),
                 bit_exact_vs_alone=bool(same), hbm_budget_gib=args.serve_budget_gib,
                 server=dict(draws_per_s=draws / span_srv, span_s=span_srv, **latencies(lat_srv),

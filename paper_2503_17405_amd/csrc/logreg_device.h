@@ -5,6 +5,7 @@
 #pragma once
 #include "fsmmc_device.h"
 #include "fsmmc_internal.h"
+#include <type_traits>
 
 namespace fsmmc {
 
