@@ -166,6 +166,7 @@ def bench_ess(F, ctx, args):
                R_hat_m=Dx.r_of_m(counts, m))
     res["effective"] = ess_report(out, t_fsm)
     res["_moments"] = Dx.moments(out[:, :, :4].double().cpu().numpy())
+    res["_sample"] = out[:64, :100].double().cpu().numpy()
     g_ms, g_n = st["kernel_ms"][0], st["kernel_launches"][0]
     flops = float(m) * n * D * (D + 1)
     # in the job, each window's GEMM shares the chip with the previous window's FSM kernel
@@ -248,6 +249,9 @@ def bench_nuts(F, ctx, args):
                mean_loop=float(counts.mean()), mean_max_loop=float(counts.max(axis=0).mean()),
                R_hat_m=Dx.r_of_m(counts, m), divergent_free=bool(np.isfinite(counts).all()))
     res["effective"] = ess_report(out, t_fsm)
+    res["_check"] = dict(moments=Dx.moments(out[:, :, :4].double().cpu().numpy()),
+                         sample=out[:64, :100].double().cpu().numpy(), X=d["X"], y=d["y"],
+                         x0=lap["x0"][:64].astype(np.float32).astype(np.float64), seed=seed, eps=0.05, depth=10)
     g_ms = st["kernel_ms"][0]
     flops = 4.0 * N * D * st["steps"]  # X Theta and X^T r per requested gradient
     g_tf = flops / (g_ms * 1e-3) / 1e12
@@ -547,6 +551,9 @@ def bench_batch(F, ctx, args):
     for j in jobs:
         j.free()
     sums = [checksum(o) for o in outs]
+    from paper_2503_17405_amd import diagnostics as Dx
+    check = dict(moments=Dx.moments(outs[-1][:, :, :4].double().cpu().numpy()),
+                 sample=outs[-1][:64, :200].double().cpu().numpy(), seed=jobs_spec[-1][5], dim=10)
     log("C4 one job at a time")
     t_alone = 0.0
     for k in range(len(jobs_spec)):
@@ -565,7 +572,7 @@ def bench_batch(F, ctx, args):
                 jobs=len(jobs_spec), draws=draws, batch_s=t_batch, alone_s=t_alone,
                 draws_per_s_batch=draws / t_batch, draws_per_s_alone=draws / t_alone,
                 speedup=t_alone / t_batch, bit_exact_vs_alone=bool(same), rounds=st["rounds"],
-                captures=st["captures"], gpu_ms=st["gpu_ms"], tuned=dict(window=st["window"],
+                captures=st["captures"], gpu_ms=st["gpu_ms"], _check=check, tuned=dict(window=st["window"],
                 dr_chunk=st["dr_chunk"], gemm_cols=st["gemm_cols"], trials=st["tune_trials"],
                 tune_ms=st["tune_ms"]))
 
@@ -724,7 +731,58 @@ def cpu_baseline(w, seed, chains, draws, threads, gpu_moments=None):
             oracle_var=[float(v) for v in om["var"]], **z,
             note="GPU: every chain of the FP32 job; oracle: the FP64 chains above; |z| in units of "
                  "the combined MCSE")
-    return res
+    return res, R
+
+
+def parted_fraction(G, R, tol=1e-4):
+    """Fraction of chains whose GPU draws leave the oracle's (relative error
+    above tol at some draw of the window): the flip fraction of the parity
+    tests, where a chain parts at a near-tie accept/reject decision."""
+    import numpy as np
+    num = np.linalg.norm(G - R, axis=2)
+    den = np.maximum(np.linalg.norm(R, axis=2), 1e-30)
+    bad = (num / den > tol).any(axis=1)
+    return dict(chains=int(G.shape[0]), draws=int(G.shape[1]), parted=int(bad.sum()),
+                flip_frac=float(bad.mean()), tol=tol)
+
+
+def oracle_checks(ess_sample, R_ess, nuts_check, batch_check, threads):
+    """Posterior moments against the FP64 oracle in MCSE units and the flip
+    fraction, for the C2 (ESS), C3 (NUTS) and C4 (DR) jobs of this run; the
+    oracle runs here, in the CPU leg, on bounded samples."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_2503_17405_amd import diagnostics as Dx
+    out = {}
+    if ess_sample is not None and R_ess is not None:
+        k = min(ess_sample.shape[0], R_ess.shape[0])
+        n = min(ess_sample.shape[1], R_ess.shape[1])
+        out["C2_ess"] = parted_fraction(ess_sample[:k, :n], R_ess[:k, :n])
+    if nuts_check is not None:
+        c = nuts_check
+        t0 = time.perf_counter()
+        tg = O.logreg_target(c["X"].astype(np.float64), c["y"])
+        m, n = c["sample"].shape[0], c["sample"].shape[1]
+        R, _, _ = O.run_chains(tg, O.nuts_sampler(c["eps"], c["depth"]), c["seed"], range(m), n, x0=c["x0"],
+                               threads=threads)
+        z = Dx.z_scores(c["moments"], Dx.moments(R[:, :, :4]))
+        out["C3_nuts"] = dict(flip=parted_fraction(c["sample"], R), **z,
+                              oracle_sample="%d chains x %d draws, %.1f s" % (m, n, time.perf_counter() - t0),
+                              note="moments: GPU every chain and draw, oracle the sample; first four coordinates")
+    if batch_check is not None:
+        c = batch_check
+        t0 = time.perf_counter()
+        tg, sp = O.funnel_target(c["dim"]), O.dr_sampler((1.0, 0.3, 0.1))
+        Rm, _, _ = O.run_chains(tg, sp, c["seed"], range(1024), c["sample"].shape[1], threads=threads)
+        m = c["sample"].shape[0]
+        z = Dx.z_scores(c["moments"], Dx.moments(Rm[:, :, :4]))
+        out["C4_dr"] = dict(flip=parted_fraction(c["sample"], Rm[:m]), **z,
+                            oracle_sample="1024 chains x %d draws, %.1f s" % (c["sample"].shape[1],
+                                                                             time.perf_counter() - t0),
+                            note="funnel D=10: coordinate 0 is v; moments: GPU every chain and draw of the "
+                                 "65536-chain job, oracle the sample")
+    return out
 
 
 def main():
@@ -824,11 +882,19 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(os.cpu_count() or 1, 16)
-        cpu = cpu_baseline(w, seed, args.cpu_chains_per_thread * threads, args.cpu_draws, threads,
-                           ess.get("_moments"))
+        cpu, R_ess = cpu_baseline(w, seed, args.cpu_chains_per_thread * threads, args.cpu_draws, threads,
+                                  ess.get("_moments"))
         log("cpu oracle: %.3g draws/s (%s)" % (cpu["value"], cpu["sample"]))
+        cpu["checks"] = oracle_checks(ess.get("_sample"), R_ess, nuts.get("_check") if nuts else None,
+                                      batch.get("_check") if batch else None, threads)
+        log("oracle checks: %s" % json.dumps(cpu["checks"]))
 
     ess.pop("_moments", None)
+    ess.pop("_sample", None)
+    if nuts:
+        nuts.pop("_check", None)
+    if batch:
+        batch.pop("_check", None)
     g = ess["gemm"]
     line = {
         "metric": METRIC,
