@@ -599,11 +599,63 @@ def serve_stream(n_jobs, seed):
     return out
 
 
+def nuts_step_cost(F):
+    """Microseconds per NUTS runtime step (transition, compaction, gradient)
+    for small logistic-regression jobs of the serving mix, alone (single-job
+    API) and as the only job of a server (its batch rounds of 16 steps);
+    wall time over the steps issued, same draws both ways."""
+    import numpy as np
+    import torch
+
+    from paper_2503_17405_amd import inputs
+    ctx = F.Context(0)
+    res = []
+    for m, D, N, n in [(16, 10, 1000, 40), (128, 50, 5000, 20), (1024, 20, 2000, 20)]:
+        d = inputs.logreg(n_data=N, dim=D, seed=7)
+        lap = inputs.logreg_laplace(d["X"], d["y"], m, seed=8)
+        eps = min(0.05, 1.0 / np.sqrt(float(np.linalg.eigvalsh(lap["hessian"])[-1])))
+        X = torch.tensor(d["X"], dtype=torch.float32, device="cuda")
+        y = torch.tensor(d["y"], dtype=torch.float32, device="cuda")
+        x0 = torch.tensor(lap["x0"], dtype=torch.float32, device="cuda")
+        tg, smp = F.logreg_target(X, y), F.nuts_sampler(eps, 10)
+        outs = []
+        for timing in (True, False):  # the timed run counts the steps, the untimed one is clocked
+            out = torch.empty((m, n, D), dtype=torch.float32, device="cuda")
+            j = F.Job(ctx, tg, smp, m, n, 11, x0=x0, out=out, timing=timing)
+            t0 = time.perf_counter()
+            while not j.step_fsm(0):
+                pass
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            st = j.stats()
+            j.free()
+            if timing:
+                steps = st["kernel_launches"][0]
+            outs.append(out)
+        srv = F.Server(ctx)
+        out_s = torch.empty_like(outs[1])
+        srv.submit(tg, smp, m, n, 11, out_s, x0=x0)
+        while not srv.wait(10.0):
+            pass
+        rec = srv.poll(8)[0]
+        sst = srv.stats()
+        srv.close()
+        ssteps = 16 * sst["rounds"]
+        res.append(dict(m=m, D=D, N=N, n=n, steps_alone=int(steps), us_per_step_alone=wall / steps * 1e6,
+                        steps_server=int(ssteps), us_per_step_server=(rec["t_done"] - rec["t_admit"]) / ssteps * 1e6,
+                        same=bool(torch.equal(outs[1], out_s) and torch.equal(outs[0], outs[1]))))
+        log("  NUTS step m=%d D=%d N=%d: %.1f us alone (%d steps), %.1f us in the server (%d steps)"
+            % (m, D, N, res[-1]["us_per_step_alone"], steps, res[-1]["us_per_step_server"], ssteps))
+    ctx.close()
+    return res
+
+
 def bench_serve(F, args):
     import numpy as np
     import torch
 
     from paper_2503_17405_amd import inputs
+    step_cost = nuts_step_cost(F)
     stream = serve_stream(args.serve_jobs, 5001)
     log("C5 stream: %d jobs, preparing inputs" % len(stream))
     t0 = time.perf_counter()
@@ -685,7 +737,7 @@ def bench_serve(F, args):
                        "the one-job-at-a-time leg of the whole stream would take about %.0f minutes at "
                        "this prefix's rate" % (len(stream), t_done / len(stream) * 2000 / 60.0)
                        if len(stream) < 2000 else None,
-                jobs=len(stream), draws=draws, host_prep_s=prep_s, all_ok=bool(ok),
+                jobs=len(stream), draws=draws, host_prep_s=prep_s, all_ok=bool(ok), nuts_step_us=step_cost,
                 bit_exact_vs_alone=bool(same), hbm_budget_gib=args.serve_budget_gib,
                 server=dict(draws_per_s=draws / span_srv, span_s=span_srv, **latencies(lat_srv),
                             rounds=sst["rounds"], gpu_ms=sst["gpu_ms"], peak_live_jobs=sst["peak_live_jobs"],

@@ -188,7 +188,22 @@ __global__ __launch_bounds__(512) void batch_grad_kernel(const BJob* jobs_in, co
     const ConstBJob* jobs = (const ConstBJob*)jobs_in;
     const BGrad t = tiles[blockIdx.x];
     const GradK& a = *(const GradK*)&jobs[t.job].grad;
-    logreg_grad_tile<DT>(a, t.ct, t.sl, lds);
+    // the job's dimension class fixed at compile time, as in the single-job
+    // kernel (a runtime class leaves the tile's per-k arrays in scratch)
+#define FSMMC_TILE_CASE(K) \
+    case K: logreg_grad_tile<DT, (K)>(a, t.ct, t.sl, lds); break;
+    if constexpr (DT == 2) {
+        switch ((a.D + 7) >> 3) {
+            FSMMC_TILE_CASE(1) FSMMC_TILE_CASE(2) FSMMC_TILE_CASE(3) FSMMC_TILE_CASE(4)
+            FSMMC_TILE_CASE(5) FSMMC_TILE_CASE(6) FSMMC_TILE_CASE(7) default: logreg_grad_tile<DT, 8>(a, t.ct, t.sl, lds);
+        }
+    } else {
+        switch ((a.D + 7) >> 3) {
+            FSMMC_TILE_CASE(9) FSMMC_TILE_CASE(10) FSMMC_TILE_CASE(11) FSMMC_TILE_CASE(12)
+            FSMMC_TILE_CASE(13) FSMMC_TILE_CASE(14) FSMMC_TILE_CASE(15) default: logreg_grad_tile<DT, 16>(a, t.ct, t.sl, lds);
+        }
+    }
+#undef FSMMC_TILE_CASE
 }
 
 // Block i: job i's chains short of n and its draws so far.

@@ -581,14 +581,20 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
         d.N = target->n_data;
         // Row slices of the gradient: about 512 (128-chain tile, slice) blocks at
         // full load -- two rounds of the blocks the chip holds at once -- with
-        // slices of 256 .. 1280 rows, a multiple of the 32-row chunk (measured
+        // slices of up to 1280 rows, a multiple of the 32-row chunk (measured
         // with the FP32 tile at N = 10^4, m = 8192: 8 slices of 1280 rows beat 20
-        // of 512 by 5%, 5 of 2048 lose 9%)
+        // of 512 by 5%, 5 of 2048 lose 9%).  Slices go below 256 rows only while
+        // the partial sums the transition adds stay within 2^20 floats per step:
+        // a job of few chains then spreads its rows over many blocks instead of
+        // walking them chunk after chunk in a handful (16 chains, N = 1000: 32
+        // blocks of one chunk instead of 4 of eight).
         {
             const int tiles = (m + 127) / 128;
             const int want = std::max(1, (512 + tiles - 1) / tiles);
             const int rows = ((d.N + want - 1) / want + 31) / 32 * 32;
-            d.slice_rows = std::min(1280, std::max(256, rows));
+            const int cap = std::max(1, (1 << 20) / ((int)m * (int)Dp));
+            const int rows_min = std::min(256, std::max(32, ((d.N + cap - 1) / cap + 31) / 32 * 32));
+            d.slice_rows = std::min(1280, std::max(rows_min, rows));
         }
         d.nslices = (d.N + d.slice_rows - 1) / d.slice_rows;
         d.Np = d.nslices * d.slice_rows;

@@ -117,6 +117,9 @@ struct SliceGrad {
         float ll = 0.0f;
 #pragma unroll
         for (int e = 0; e < EPL; ++e) g.r[e] = 0.0f;
+        // unrolled so that the loads of several slices are in flight at once
+        // (the additions keep their order)
+#pragma unroll 8
         for (int s = 0; s < a.nslices; ++s) {
             const float* gp = a.Gpart + ((size_t)s * a.m + c) * a.Dp;
 #pragma unroll
