@@ -220,6 +220,19 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
  * not NULL it receives 1 when every chain has n_draws draws, else 0. */
 fsmmc_status fsmmc_step_fsm(fsmmc_job* job, int64_t max_steps, int32_t* all_done);
 
+/* fsmmc_step_fsm without waiting: the steps are queued on the job's stream
+ * and the call returns; nothing is read back from the device (chains meet
+ * only at their n-th draw, Sec. 3.2, so the host need not watch them).  When
+ * the queued work has run, *done holds 1 if every chain has n_draws draws,
+ * else 0; done must be device memory or pinned host memory (hipHostMalloc),
+ * read after fsmmc_job_sync or after an event recorded on the job's stream.
+ * The draws are those of fsmmc_step_fsm.  max_steps as there; for NUTS on
+ * logistic regression max_steps must be > 0 (the number of runtime steps to
+ * the last draw is not known ahead), and the call queues max_steps + 1 of
+ * them.  Errors: EINVAL (NULL or pageable done, NUTS without a budget),
+ * EBUSY (the job belongs to a batch), EDEVICE. */
+fsmmc_status fsmmc_step_fsm_async(fsmmc_job* job, int64_t max_steps, int32_t* done);
+
 /* Produce the next n_draws draws of every chain in lock step: draw i of all
  * chains completes before any chain starts draw i+1 (Appendix, Alg.
  * "Vectorized MCMC algorithm with vmap(sample)").  mode is an

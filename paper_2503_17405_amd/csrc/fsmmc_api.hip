@@ -30,6 +30,15 @@ __global__ void fill_i32_kernel(int32_t* p, int32_t v, int n)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
+// *done = 1 when every chain holds n draws, else 0 (one block).
+__global__ void all_done_kernel(const uint32_t* t, int m, uint32_t n, int32_t* done)
+{
+    int ok = 1;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) ok &= t[i] >= n ? 1 : 0;
+    ok = __syncthreads_and(ok);
+    if (threadIdx.x == 0) *done = ok;
+}
+
 }  // namespace
 
 fsmmc_status fail(fsmmc_status s, const std::string& msg)
@@ -904,6 +913,79 @@ fsmmc_status fsmmc_step_fsm(fsmmc_job* job, int64_t max_steps, int32_t* all_done
         if (active == 0 || job->h_ctr[3] == 0) break;
     }
     if (all_done) *all_done = active == 0 ? 1 : 0;
+    return FSMMC_OK;
+}
+
+// The FSM runtime without host reads: every round a chain runs to the end of
+// its window (W draws) or of its budget, so ceil((n - t_lo) / W) rounds take
+// every chain to n or to the end of its budget; rounds past that find no
+// chain to step (their kernels return at once).  NUTS: a live chain with
+// budget asks for one gradient per runtime step, so max_steps + 1 steps (the
+// last one consumes the last gradient) leave it where fsmmc_step_fsm would.
+fsmmc_status fsmmc_step_fsm_async(fsmmc_job* job, int64_t max_steps, int32_t* done)
+{
+    if (!job) return fail(FSMMC_EINVAL, "job is NULL");
+    if (job->batch) return fail(FSMMC_EBUSY, "job is stepped by a batch or server");
+    if (!done) return fail(FSMMC_EINVAL, "done is NULL");
+    JobDev& d = job->d;
+    HIP_TRY(hipSetDevice(job->ctx->device));
+    hipPointerAttribute_t pa{};
+    if (hipPointerGetAttributes(&pa, done) != hipSuccess ||
+        (pa.type != hipMemoryTypeDevice && pa.type != hipMemoryTypeHost && pa.type != hipMemoryTypeManaged) ||
+        !pa.devicePointer) {
+        (void)hipGetLastError();
+        return fail(FSMMC_EINVAL, "done must be device memory or pinned (hipHostMalloc) host memory");
+    }
+    const bool nuts_lr = d.kind == FSMMC_NUTS && d.target == FSMMC_LOGREG;
+    if (nuts_lr && max_steps <= 0)
+        return fail(FSMMC_EINVAL, "asynchronous NUTS on logistic regression needs max_steps > 0 (its length is "
+                                  "not known ahead)");
+    hipStream_t s = job->stream;
+    const uint32_t n = (uint32_t)d.n;
+    const int64_t b = max_steps > 0 ? max_steps : INT64_MAX;
+    const int K = (int)((n - std::min(job->t_lo, n) + (uint32_t)d.W - 1) / (uint32_t)std::max(1, d.W));
+    d.tstop = n;
+    HIP_TRY(fill_i64(d.budget, b, d.m, s));
+    job->launches++;
+    if (nuts_lr) {
+        for (int64_t i = 0; i <= max_steps; ++i) {
+            const uint32_t st = job->step;
+            HIP_TRY(launch(job, KC_FSM, [&] { return nuts_transition(d, 0, st, s); }));
+            HIP_TRY(launch(job, KC_G, [&] { return nuts_gradient(d, s); }));
+            job->step++;
+        }
+    } else if (d.kind == FSMMC_NUTS) {  // mixture: one persistent launch
+        HIP_TRY(launch(job, KC_FSM, [&] { return mog_run(d, 0, 0, &job->qticket, s); }));
+    } else if (d.kind == FSMMC_ESS && d.target == FSMMC_GP_HYPER) {
+        HIP_TRY(launch(job, KC_FSM, [&] { return gph_run(d, 0, 0, &job->qticket, s); }));
+    } else if (d.kind == FSMMC_DRSYM) {
+        HIP_TRY(hipMemsetAsync(d.ctr + 3, 0, 2 * sizeof(unsigned long long), s));
+        HIP_TRY(launch(job, KC_FSM, [&] { return drs_fsm_round(d, s); }));
+    } else if (d.kind == FSMMC_DRMH) {
+        HIP_TRY(hipMemsetAsync(d.ctr + 3, 0, 2 * sizeof(unsigned long long), s));
+        HIP_TRY(launch(job, KC_FSM, [&] { return dr_fsm_round(d, s); }));
+    } else if (d.kind == FSMMC_SLICE) {
+        for (int k = 0; k < K; ++k) {
+            HIP_TRY(hipMemsetAsync(d.ctr + 3, 0, 2 * sizeof(unsigned long long), s));
+            HIP_TRY(launch(job, KC_G, [&] { return sl_dir_window(d, s); }));
+            HIP_TRY(launch(job, KC_FSM, [&] { return sl_fsm_round(d, s); }));
+        }
+    } else if (max_steps <= 0) {  // ESS, every chain to n: pipelined windows
+        if (K > 0) {
+            fsmmc_status st = ess_windows(job, -1, 0, 0, K);
+            if (st != FSMMC_OK) return st;
+        }
+    } else {  // ESS with a budget: windows one after another
+        for (int k = 0; k < K; ++k) {
+            HIP_TRY(hipMemsetAsync(d.ctr + 3, 0, 2 * sizeof(unsigned long long), s));
+            HIP_TRY(launch(job, KC_G, [&] { return ess_fill_window(d, s); }));
+            HIP_TRY(launch(job, KC_FSM, [&] { return ess_fsm_round(d, s); }));
+        }
+    }
+    hipLaunchKernelGGL(all_done_kernel, dim3(1), dim3(256), 0, s, (const uint32_t*)d.t, d.m, n,
+                       (int32_t*)pa.devicePointer);
+    HIP_TRY(hipGetLastError());
+    if (max_steps <= 0) job->t_lo = n;
     return FSMMC_OK;
 }
 

@@ -56,6 +56,7 @@ struct fsmmc_job {
     unsigned long long* h_ctr = nullptr;  // pinned: [0..7] mirror of d.ctr, [8..15] scratch reads
     int launches = 0;
     uint32_t step = 0;  // NUTS runtime step counter (keys the per-step counters)
+    uint32_t t_lo = 0;  // every chain holds at least t_lo draws (known without reading the device)
     unsigned long long qticket = 0;  // NUTS on a mixture: chain-queue base of the next launch
     fsmmc_batch* batch = nullptr;  // the batch or server that owns the job's stepping, if any
     // ESS: the next window's ellipse GEMM runs on a side stream while the

@@ -25,7 +25,8 @@ SYNC_VMAP, SYNC_COMPACT = 0, 1
 # every symbol the header declares
 EXPORTS = [
     "fsmmc_ctx_create", "fsmmc_ctx_destroy", "fsmmc_ctx_bytes_in_use", "fsmmc_init_chains",
-    "fsmmc_step_fsm", "fsmmc_step_synchronized", "fsmmc_collect_samples", "fsmmc_collect_counts",
+    "fsmmc_step_fsm", "fsmmc_step_fsm_async", "fsmmc_step_synchronized", "fsmmc_collect_samples",
+    "fsmmc_collect_counts",
     "fsmmc_chain_progress", "fsmmc_job_stats", "fsmmc_job_sync", "fsmmc_job_free",
     "fsmmc_last_error", "fsmmc_version", "fsmmc_eval_potential", "fsmmc_eval_potential_noalloc",
     "fsmmc_batch_create", "fsmmc_batch_run", "fsmmc_batch_stats", "fsmmc_batch_free",
@@ -120,6 +121,7 @@ def _load():
         "fsmmc_ctx_bytes_in_use": ([p], sz),
         "fsmmc_init_chains": ([p, p, p, i32, i32, u64, p, p, p, p, pp], C.c_int),
         "fsmmc_step_fsm": ([p, i64, p], C.c_int),
+        "fsmmc_step_fsm_async": ([p, i64, p], C.c_int),
         "fsmmc_step_synchronized": ([p, i32, i32, p], C.c_int),
         "fsmmc_collect_samples": ([p, i32, i32, p, i32], C.c_int),
         "fsmmc_collect_counts": ([p, p], C.c_int),
@@ -204,6 +206,16 @@ def fsmmc_step_fsm(job, max_steps=0):
     done = C.c_int32()
     _check(lib.fsmmc_step_fsm(job, max_steps, C.byref(done)))
     return bool(done.value)
+
+
+def fsmmc_step_fsm_async(job, max_steps, done):
+    """done: an int32 tensor on the device or in pinned host memory (the
+    library rejects pageable memory); its first element is written when the
+    queued steps have run."""
+    import torch
+    if done.dtype != torch.int32 or done.numel() < 1:
+        raise ValueError("done must be an int32 tensor with at least one element")
+    _check(lib.fsmmc_step_fsm_async(job, max_steps, C.c_void_p(done.data_ptr())))
 
 
 def fsmmc_step_synchronized(job, n_draws, mode=SYNC_VMAP):
@@ -378,6 +390,9 @@ class Job:
 
     def step_fsm(self, max_steps=0):
         return fsmmc_step_fsm(self.handle, max_steps)
+
+    def step_fsm_async(self, max_steps, done):
+        fsmmc_step_fsm_async(self.handle, max_steps, done)
 
     def step_synchronized(self, n_draws, mode=SYNC_VMAP):
         return fsmmc_step_synchronized(self.handle, n_draws, mode)
