@@ -879,6 +879,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=40)
     ap.add_argument("--serve-budget-gib", type=int, default=64)
+    ap.add_argument("--no-ceilings", action="store_true")
     ap.add_argument("--calib-copy-gib", type=int, default=0,
                     help="also run a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -902,6 +903,18 @@ def main():
         del a, b
         torch.cuda.empty_cache()
 
+    ceilings = None
+    if not args.no_ceilings and not args.tune_mog_eps:
+        # the units' measured rates beside the spec peaks the rooflines use
+        meas = F.measure_ceilings(0)
+        ceilings = dict(measured=meas, spec=dict(
+            hbm_gbps=8000.0, mfma_bf16_tflops=PEAK_MFMA_BF16, mfma_f32_tflops=PEAK_MFMA_F32,
+            valu_f32_tflops=157.3, valu_f64_tflops=78.6,
+            note="spec FP32 vector 157.3 counts packed FP32 (two lanes' worth per instruction); this "
+                 "library never emits packed FP32, so its vector FP32 ceiling is half of that"))
+        log("ceilings: copy %.0f GB/s, bf16 MFMA %.0f TFLOP/s, FP32 MFMA %.1f, FP32 FMA %.1f, FP64 FMA %.1f, "
+            "exp2 %.0f G/s" % (meas["hbm_copy_gbps"], meas["mfma_bf16_tflops"], meas["mfma_f32_tflops"],
+                               meas["valu_f32_tflops"], meas["valu_f64_tflops"], meas["exp_f32_gops"]))
     ctx = F.Context(0)
     if args.tune_mog_eps:
         eps = tune_mog_step_size(F, ctx)
@@ -981,7 +994,10 @@ def main():
                      "executed_bf16_tflops": PIECE_PRODUCTS * g["tflops"],
                      "isolated": {"achieved": ess["gemm_isolated"]["tflops"],
                                   "frac": ess["gemm_isolated"]["tflops"] / PEAK_GEMM,
-                                  "avg_launch_us": ess["gemm_isolated"]["avg_us"]}},
+                                  "avg_launch_us": ess["gemm_isolated"]["avg_us"]},
+                     "frac_of_measured_peak": (g["tflops"] / (ceilings["measured"]["mfma_bf16_tflops"]
+                                                             / PIECE_PRODUCTS)) if ceilings else None},
+        "ceilings": ceilings,
         "ess": ess,
         "speedup_vs_sync_vmap": ess["sync"].get("vmap", {}).get("speedup_fsm"),
         "speedup_vs_sync_compact": ess["sync"].get("compact", {}).get("speedup_fsm"),

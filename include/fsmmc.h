@@ -454,6 +454,27 @@ const char* fsmmc_last_error(void);
 /* Library version string. */
 const char* fsmmc_version(void);
 
+/* ---------------------------------------------------------------- ceilings
+ * Measured rates of the units the hot path runs on, to set beside the
+ * spec-sheet peaks its rooflines are quoted against (the paper reports
+ * throughput only; these are the denominators of the roofline fractions).  */
+typedef struct {
+    double hbm_copy_gbps;    /* device-to-device copy: (read + write bytes) / s, 1e9 units      */
+    double mfma_bf16_tflops; /* v_mfma_f32_32x32x16_bf16 with independent accumulators          */
+    double mfma_f32_tflops;  /* v_mfma_f32_32x32x2_f32                                           */
+    double valu_f32_tflops;  /* vector FP32 FMA, unpacked (this library never emits packed FP32) */
+    double valu_f64_tflops;  /* vector FP64 FMA                                                  */
+    double exp_f32_gops;     /* hardware exp2 results per second, 1e9 units                      */
+    int32_t cus;             /* compute units                                                    */
+    int32_t clock_mhz;       /* peak engine clock reported by the runtime                        */
+} fsmmc_ceilings;
+
+/* Run the measurement kernels on `device` (about a second) and fill *out.
+ * copy_bytes: size of each of the two copy buffers (>= 64 MiB, a multiple of
+ * 16); the call allocates and frees them and a small result buffer, and
+ * synchronises the device.  Errors: EINVAL, EDEVICE (including out of memory). */
+fsmmc_status fsmmc_measure_ceilings(int device, size_t copy_bytes, fsmmc_ceilings* out);
+
 #ifdef __cplusplus
 }
 #endif

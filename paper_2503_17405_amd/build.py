@@ -17,7 +17,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfsmmc.so")
 
-SOURCES = ["fsmmc_api.hip", "ess.hip", "nuts.hip", "logreg.hip", "dr.hip", "batch.hip", "serve.hip", "mog.hip", "drsym.hip", "slice.hip", "gph.hip"]
+SOURCES = ["fsmmc_api.hip", "ess.hip", "nuts.hip", "logreg.hip", "dr.hip", "batch.hip", "serve.hip", "mog.hip", "drsym.hip", "slice.hip", "gph.hip",
+           "ceilings.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",

@@ -31,7 +31,7 @@ EXPORTS = [
     "fsmmc_last_error", "fsmmc_version", "fsmmc_eval_potential", "fsmmc_eval_potential_noalloc",
     "fsmmc_batch_create", "fsmmc_batch_run", "fsmmc_batch_stats", "fsmmc_batch_free",
     "fsmmc_clock", "fsmmc_server_create", "fsmmc_server_submit", "fsmmc_server_poll",
-    "fsmmc_server_wait", "fsmmc_server_stats", "fsmmc_server_destroy",
+    "fsmmc_server_wait", "fsmmc_server_stats", "fsmmc_server_destroy", "fsmmc_measure_ceilings",
 ]
 
 
@@ -102,6 +102,15 @@ class ServerCounters(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class Ceilings(C.Structure):
+    _fields_ = [("hbm_copy_gbps", C.c_double), ("mfma_bf16_tflops", C.c_double), ("mfma_f32_tflops", C.c_double),
+                ("valu_f32_tflops", C.c_double), ("valu_f64_tflops", C.c_double), ("exp_f32_gops", C.c_double),
+                ("cus", C.c_int32), ("clock_mhz", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class FsmmcError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("fsmmc error %d: %s" % (status, msg))
@@ -144,6 +153,7 @@ def _load():
         "fsmmc_server_destroy": ([p], C.c_int),
         "fsmmc_last_error": ([], C.c_char_p),
         "fsmmc_version": ([], C.c_char_p),
+        "fsmmc_measure_ceilings": ([C.c_int, sz, p], C.c_int),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
@@ -157,6 +167,12 @@ lib = _load()
 def _check(status):
     if status != OK:
         raise FsmmcError(status, lib.fsmmc_last_error().decode())
+
+
+def measure_ceilings(device=0, copy_bytes=2 << 30):
+    out = Ceilings()
+    _check(lib.fsmmc_measure_ceilings(device, copy_bytes, C.byref(out)))
+    return out.as_dict()
 
 
 def version():
