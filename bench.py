@@ -466,8 +466,8 @@ def bench_gphyper(F, ctx, args):
     from paper_2503_17405_amd import inputs
     res = dict(workload="ESS on GP-regression hyperparameters: n observations with 6 inputs (synthetic "
                         "stand-in for the 6-feature regression data), N(0,I) prior on (tau, lambda, sigma), "
-                        "FP64 Cholesky per likelihood, %d chains x %d draws (%d draws for n > 128, where "
-                        "a block of four waves factors each matrix)"
+                        "FP64 Cholesky per likelihood, %d chains x %d draws (%d draws for n > 128); the "
+                        "chain's wave factors each matrix for n <= 96, a block of four waves above"
                         % (args.gph_chains, args.gph_draws, args.gph_big_draws),
                runs={})
     m = args.gph_chains

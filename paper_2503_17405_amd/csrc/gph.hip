@@ -21,7 +21,7 @@
 //     the trailing triangle, four columns at a time; a block barrier (one
 //     wave) orders the LDS updates;
 //   * log L = -|z|^2 / 2 - sum_j log L_jj; -inf when a pivot is not positive.
-// More than 128 observations (the paper's data set has 414): one block of
+// More than 96 observations (the paper's data set has 414): one block of
 // four waves per chain (gph_big_kernel), C in a global slot of the block
 // (n rounded up to 32, identity padding), blocked right-looking Cholesky
 // with 32-column panels:
@@ -42,7 +42,7 @@
 
 namespace fsmmc {
 
-constexpr int kGphMaxN = 128;     // observations, in-wave likelihood: two rows per lane
+constexpr int kGphMaxN = 96;      // observations, in-wave likelihood: up to two rows per lane
 constexpr int kGphBigMaxN = 512;  // observations, block likelihood (LDS holds a 32-column panel)
 constexpr int kGphBigWaves = 4;   // waves per block of the block likelihood
 constexpr int kGphMaxP = 16;      // input dimension
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(64) void gph_init_kernel(GphK a, int has_x0)
     }
 }
 
-// ------------------------------------------------------------ n > 128
+// ------------------------------------------------------------ n > 96
 // LDS of the block likelihood, in doubles: the panel below the diagonal block
 // [32][ld - 32] (column t, row r), the diagonal block [32][33], the
 // reciprocal pivots [32], y [ld], and 8 scalars.
@@ -493,7 +493,7 @@ __device__ __forceinline__ int gph_block_next_chain(unsigned long long* q, unsig
     return *sh;
 }
 
-// The block forms of gph_kernel and gph_init_kernel (n > 128).
+// The block forms of gph_kernel and gph_init_kernel (n > 96).
 __global__ __launch_bounds__(64 * kGphBigWaves) void gph_big_kernel(GphK a, unsigned long long* q, unsigned long long base, int mode,
                                                       uint32_t draw)
 {

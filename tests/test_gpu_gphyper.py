@@ -1,7 +1,7 @@
 """GPU parity of elliptical slice sampling on GP-regression hyperparameters
 (Sec. 7.2): an O(n^3) Cholesky of the n x n kernel matrix inside every loop
-iteration, computed in FP64 by the chain's wavefront (n <= 128) or by a
-block with a blocked factorisation (n > 128).  FSM runtime ==
+iteration, computed in FP64 by the chain's wavefront (n <= 96) or by a
+block with a blocked factorisation (n > 96).  FSM runtime ==
 synchronized runtime (vmap and compact) bit for bit; draws match the FP64
 oracle per draw (1e-9 relative: both sides FP64, the factorisations add up
 in different orders)."""
@@ -64,13 +64,14 @@ def test_gphyper_runtimes_bit_exact(F, ctx, nobs, m, n):
           % (nobs, C0.mean(), m, C0.max(axis=0).mean(), st0["r_hat"]))
 
 
-@pytest.mark.parametrize("nobs", [1, 25, 100, 128, 129, 250, 414])
+@pytest.mark.parametrize("nobs", [1, 25, 64, 65, 96, 97, 100, 128, 129, 250, 414])
 def test_gphyper_oracle_parity(F, ctx, nobs):
-    # 129 .. 414: the block factorisation (a ragged last panel at 129, 250 and
-    # 414; 414 is the paper's data size)
+    # up to 96: the chain's wave (one row per lane up to 64, two above);
+    # 97 .. 414: the block factorisation (a ragged last panel at 97, 100, 129,
+    # 250 and 414; 414 is the paper's data size)
     m = 32 if nobs <= 128 else 8
     w = inputs.gp_hyper(n=nobs, n_chains=m, seed=20 + nobs)
-    n, seed = (100 if nobs < 100 else 40 if nobs <= 128 else 12), 21 + nobs
+    n, seed = (100 if nobs < 96 else 40 if nobs <= 128 else 12), 21 + nobs
     x0 = w["x0"]
     S, C, _ = run(F, ctx, w, m, n, seed, x0=x0)
     tg = O.gp_hyper_target(w["X"], w["y"], w["jitter"])
