@@ -65,7 +65,7 @@ def check_parity(S, C, R, RC, tg, seed, eps, J, x0, first, chains=None):
                                first=first)
 
 
-@pytest.mark.parametrize("N,D", [(2000, 20), (10000, 100), (777, 3), (1, 1), (513, 64)])
+@pytest.mark.parametrize("N,D", [(2000, 20), (10000, 100), (777, 3), (1, 1), (513, 64), (1001, 65), (3000, 128)])
 def test_logreg_potential_and_gradient_vs_oracle(F, ctx, N, D):
     # the fused MFMA gradient kernel against the oracle's plain sums
     d = inputs.logreg(n_data=N, dim=D, seed=N * 7 + D)
@@ -103,8 +103,11 @@ def test_nuts_fsm_equals_synchronized(F, ctx):
     assert C.min() >= 1 and C.max() <= 2 ** J - 1
 
 
-@pytest.mark.parametrize("N,D,eps,J", [(2000, 20, 0.05, 10), (777, 3, 0.1, 8), (1000, 64, 0.05, 10)])
+@pytest.mark.parametrize("N,D,eps,J", [(2000, 20, 0.05, 10), (777, 3, 0.1, 8), (1000, 64, 0.05, 10),
+                                       (1001, 65, 0.05, 8), (3000, 128, 0.03, 8)])
 def test_nuts_oracle_parity(F, ctx, N, D, eps, J):
+    # 32 chains: the rows go out in 32-row slices (a ragged last one at N = 1001);
+    # D = 65 and 128: the first and the last dimension of the wide tile
     d = inputs.logreg(n_data=N, dim=D, seed=N + D)
     m, n, seed = 32, 60, 7
     lap = inputs.logreg_laplace(d["X"], d["y"], m, seed=8)
