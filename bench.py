@@ -212,13 +212,17 @@ def bench_ess(F, ctx, args):
     return res, w, seed
 
 
-def bench_nuts(F, ctx, args):
+def bench_nuts(F, ctx, args, m=None, light=False):
+    """NUTS on the logistic-regression workload (N = 10000, D = 100, step
+    0.05, depth 10, Laplace starts).  light: FSM and synchronized timings
+    only (no kernel breakdown or oracle samples)."""
     import numpy as np
     import torch
 
     from paper_2503_17405_amd import diagnostics as Dx
     from paper_2503_17405_amd import inputs
-    m, n, N, D = args.nuts_chains, args.nuts_draws, 10000, 100
+    m = args.nuts_chains if m is None else m
+    n, N, D = args.nuts_draws, 10000, 100
     d = inputs.logreg(n_data=N, dim=D, seed=3001)
     lap = inputs.logreg_laplace(d["X"], d["y"], m, seed=3002)
     X = torch.tensor(d["X"], dtype=torch.float32, device="cuda")
@@ -249,6 +253,20 @@ def bench_nuts(F, ctx, args):
                mean_loop=float(counts.mean()), mean_max_loop=float(counts.max(axis=0).mean()),
                R_hat_m=Dx.r_of_m(counts, m), divergent_free=bool(np.isfinite(counts).all()))
     res["effective"] = ess_report(out, t_fsm)
+    if light:
+        job = None
+        sync = {}
+        if not args.no_sync:
+            for name, mode in (("vmap", F.SYNC_VMAP), ("compact", F.SYNC_COMPACT)):
+                log("NUTS sync %s (%d chains)" % (name, m))
+                dt, job = timed_jobs(make, lambda j, mode=mode: j.step_synchronized(n, mode), 1, 0)
+                job.free()
+                sync[name] = dict(seconds=dt, draws_per_s=m * n / dt, bit_exact_vs_fsm=bool(checksum(out) == ref),
+                                  speedup_fsm=dt / t_fsm)
+        res.update(chains=m, draws=n, sync=sync)
+        del out
+        torch.cuda.empty_cache()
+        return res
     res["_check"] = dict(moments=Dx.moments(out[:, :100, :4].double().cpu().numpy()),
                          sample=out[:64, :100].double().cpu().numpy(), X=d["X"], y=d["y"],
                          x0=lap["x0"][:64].astype(np.float32).astype(np.float64), seed=seed, eps=0.05, depth=10)
@@ -860,6 +878,8 @@ def main():
     ap.add_argument("--nuts-steps", type=int, default=1)
     ap.add_argument("--nuts-warmup", type=int, default=1)
     ap.add_argument("--no-nuts", action="store_true")
+    ap.add_argument("--nuts-c3-chains", type=int, default=4096,
+                    help="also run the logistic-regression NUTS job at this chain count (0: skip)")
     ap.add_argument("--no-mog", action="store_true")
     ap.add_argument("--mog-chains", type=int, nargs="+", default=[100, 500, 4096])
     ap.add_argument("--mog-draws", type=int, default=1000)
@@ -930,10 +950,13 @@ def main():
         return
     ess, w, seed = bench_ess(F, ctx, args)
     log("ESS: FSM %.3g draws/s" % ess["draws_per_s"])
-    nuts = None
+    nuts = nuts_c3 = None
     if not args.no_nuts:
         nuts = bench_nuts(F, ctx, args)
         log("NUTS: FSM %.3g draws/s" % nuts["draws_per_s"])
+        if args.nuts_c3_chains > 0:
+            nuts_c3 = bench_nuts(F, ctx, args, m=args.nuts_c3_chains, light=True)
+            log("NUTS (%d chains): FSM %.3g draws/s" % (args.nuts_c3_chains, nuts_c3["draws_per_s"]))
     mog = None
     if not args.no_mog:
         mog = bench_mog(F, ctx, args)
@@ -1009,6 +1032,7 @@ def main():
         "speedup_vs_sync_vmap": ess["sync"].get("vmap", {}).get("speedup_fsm"),
         "speedup_vs_sync_compact": ess["sync"].get("compact", {}).get("speedup_fsm"),
         "nuts": nuts,
+        "nuts_c3": nuts_c3,
         "nuts_mog": mog,
         "drsym": drsym,
         "slice": slc,
