@@ -72,7 +72,12 @@ __device__ __forceinline__ void ess_fsm_body(const EssK<T>& a)
     const int lane = threadIdx.x & 63;
     const int j = uni((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
     EssTally tl;
-    if (j < a.m) (void)ess_window_run<T, EPL, FULL>(a, j, lane, tl);
+    if (j < a.m) {
+        if (a.target == FSMMC_GP_GAUSS)
+            (void)ess_window_run<T, EPL, FULL, FSMMC_GP_GAUSS>(a, j, lane, tl);
+        else
+            (void)ess_window_run<T, EPL, FULL, FSMMC_GP_LOGISTIC>(a, j, lane, tl);
+    }
     // one atomic per block and counter
     const unsigned long long steps = block_sum_u64(tl.steps, &s_sum);
     if (threadIdx.x == 0 && steps) atomicAdd(&a.ctr[0], steps);
@@ -112,12 +117,13 @@ __device__ __forceinline__ int ess_sync_run(const EssK<T>& a, int j, int lane, u
         yv[e] = a.y[e * 64 + lane];
         nu[e] = nj[e * 64 + lane];
     }
+    const EssLin L = ess_lin_of<T, EPL, FULL>(x, nu, yv, lane, a.D, a.target);
     T lx = uni(a.lx[j]), logu, theta, tmin, tmax;
     ess_begin<T>(a.seed, (uint32_t)j, draw, logu, theta, tmin, tmax);
     int evals = 0;
     T lp;
     for (;;) {
-        lp = uni(ess_propose_eval<T, EPL, FULL>(x, nu, xp, yv, theta, lane, a.D, a.target, a.inv2v));
+        lp = uni(ess_propose_eval<T, EPL, FULL>(x, nu, xp, yv, theta, lane, a.D, a.target, a.inv2v, L));
         ++evals;
         if (lp - lx > logu || evals >= kEssMaxEvals) break;
         ess_shrink<T>(a.seed, (uint32_t)j, draw, evals, theta, tmin, tmax);
@@ -188,11 +194,12 @@ __device__ __forceinline__ int ess_pad_run(const EssK<T>& a, int j, int lane, ui
         yv[e] = a.y[e * 64 + lane];
         nu[e] = nj[e * 64 + lane];
     }
+    const EssLin L = ess_lin_of<T, EPL, FULL>(x, nu, yv, lane, a.D, a.target);
     T sum = T(0);
     for (int i = 0; i < extra; ++i) {
         const T theta = Pi<T>::two_pi * uniform<T>(a.seed, (uint32_t)j, draw, ROLE_ANGLE,
                                                     (uint32_t)(nj_evals + i));
-        sum += ess_propose_eval<T, EPL, FULL>(x, nu, xp, yv, theta, lane, a.D, a.target, a.inv2v);
+        sum += ess_propose_eval<T, EPL, FULL>(x, nu, xp, yv, theta, lane, a.D, a.target, a.inv2v, L);
     }
     if (lane == 0) a.sink[j] = sum;
     return extra;

@@ -402,13 +402,71 @@ __device__ __forceinline__ void nu_gemm_block(const NuK<float>& a, int col0)
 }
 
 // ------------------------------------------------------------ ESS blocks
+// FP32 logistic likelihood along an ellipse.  x' = x cos(theta) + nu sin(theta)
+// is linear in (x, nu), so the lane sums of y x' and of x' are
+// cos (sum y x, sum x) + sin (sum y nu, sum nu): EssLin holds the four sums,
+// formed once per (x, nu) -- per draw -- instead of once per evaluation.
+// With max(f, 0) = (f + |f|) / 2 the evaluation then spends, per element,
+// two instructions on x', one on the sum of |x'| and one FMA on the product
+// of the factors 1 + e^-|x'| (p + p e^-|x'|): each lies in (1, 2], so the
+// product of at most 16 stays in [1, 2^16], where the hardware log2 is
+// accurate, and one log replaces EPL of them (the vector units bound this
+// loop, so it is written for few instructions per element).
+struct EssLin {
+    float yx, yn, sx, sn;
+};
+
+template <int EPL, bool FULL>
+__device__ __forceinline__ EssLin ess_lin(const float (&x)[EPL], const float (&nu)[EPL], const float (&yv)[EPL],
+                                          int lane, int D)
+{
+    EssLin L{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+        const bool in = FULL || e * 64 + lane < D;
+        const float xe = in ? x[e] : 0.0f, ne = in ? nu[e] : 0.0f;
+        L.yx = fmaf(yv[e], xe, L.yx);
+        L.yn = fmaf(yv[e], ne, L.yn);
+        L.sx += xe;
+        L.sn += ne;
+    }
+    return L;
+}
+
+// Lane part of log L(x') for the FP32 logistic likelihood, x' into xp.
+template <int EPL, bool FULL>
+__device__ __forceinline__ float ess_lane_logistic_lin(const float (&x)[EPL], const float (&nu)[EPL],
+                                                       float (&xp)[EPL], float c, float s, const EssLin& L,
+                                                       int lane, int D)
+{
+    static_assert(EPL <= 16, "the factor product must stay below 2^16");
+    float asum = 0.0f, prod = 1.0f;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+        const bool in = FULL || e * 64 + lane < D;
+        const float f = fmaf(x[e], c, nu[e] * s);
+        xp[e] = f;
+        const float af = in ? fabsf(f) : 0.0f;
+        asum = e == 0 ? af : asum + af;
+        prod = fmaf(prod, in ? __expf(-fabsf(f)) : 0.0f, prod);
+    }
+    const float yf = fmaf(c, L.yx, s * L.yn), sf = fmaf(c, L.sx, s * L.sn);
+    return yf - 0.5f * (sf + asum) - 0.693147180559945309f * __builtin_amdgcn_logf(prod);
+}
+
+// log L(x) of a state (FP32 logistic): the same arithmetic at theta = 0.
+template <int EPL, bool FULL>
+__device__ __forceinline__ float ess_lane_logistic_at(const float (&x)[EPL], const float (&yv)[EPL], int lane, int D)
+{
+    float xp[EPL];
+    return ess_lane_logistic_lin<EPL, FULL>(x, x, xp, 1.0f, 0.0f, ess_lin<EPL, FULL>(x, x, yv, lane, D), lane, D);
+}
+
 // Lane-local part of log L(f) over the lane's elements d = e * 64 + lane < D.
 //   Gaussian:  -sum (y - f)^2 / (2 sd^2)
 //   logistic:  sum y f - softplus(f), softplus(f) = max(f, 0) + log(1 + e^-|f|).
-// FP32 logistic takes the log of the product of the factors 1 + e^-|f|: each
-// lies in (1, 2], so the product of at most 16 cannot overflow, and one log
-// replaces EPL of them (the vector units bound this loop, so it is written
-// for few instructions per element).
+// FP32 logistic: the arithmetic of the evaluations along an ellipse
+// (ess_lane_logistic_at).
 // FULL: D == 64 EPL, every lane element exists and the masks drop out (the
 // same operations on the same values as the masked form).
 template <typename T, int EPL, bool FULL = false>
@@ -426,20 +484,7 @@ __device__ __forceinline__ T ess_lane_loglik(const T (&f)[EPL], const T (&yv)[EP
         return acc;
     }
     if constexpr (sizeof(T) == 4) {
-        // three running sums: y f (one FMA per element), max(f, 0) (one med3
-        // and one add) and the product of the factors (one FMA: p + p e^-|f|);
-        // the product lies in [1, 2^16], where the hardware log2 is accurate
-        static_assert(EPL <= 16, "the factor product must stay below 2^16");
-        float relu = 0.0f, prod = 1.0f;
-#pragma unroll
-        for (int e = 0; e < EPL; ++e) {
-            const bool in = FULL || e * 64 + lane < D;
-            acc = fmaf(in ? yv[e] : 0.0f, f[e], acc);
-            const float r = in ? __builtin_amdgcn_fmed3f(f[e], 0.0f, 3.40282347e38f) : 0.0f;
-            relu = e == 0 ? r : relu + r;
-            prod = fmaf(prod, in ? __expf(-fabsf(f[e])) : 0.0f, prod);
-        }
-        return acc - relu - 0.693147180559945309f * __builtin_amdgcn_logf(prod);
+        return ess_lane_logistic_at<EPL, FULL>(f, yv, lane, D);
     } else {
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
@@ -451,17 +496,30 @@ __device__ __forceinline__ T ess_lane_loglik(const T (&f)[EPL], const T (&yv)[EP
 }
 
 // x' = x cos(theta) + nu sin(theta) and log L(x'), summed in a fixed order
-// (lane-local, then a wave butterfly); the result is wave-uniform.
+// (lane-local, then a wave butterfly); the result is wave-uniform.  L: the
+// sums of (x, nu) for the FP32 logistic likelihood (unused otherwise).
 template <typename T, int EPL, bool FULL = false>
 __device__ __forceinline__ T ess_propose_eval(const T (&x)[EPL], const T (&nu)[EPL], T (&xp)[EPL],
                                               const T (&yv)[EPL], T theta, int lane, int D, int target,
-                                              T inv2v)
+                                              T inv2v, const EssLin& L)
 {
     T s, c;
     M<T>::sincos_(theta, &s, &c);
+    if constexpr (sizeof(T) == 4)
+        if (target == FSMMC_GP_LOGISTIC) return wave_sum(ess_lane_logistic_lin<EPL, FULL>(x, nu, xp, c, s, L, lane, D));
 #pragma unroll
     for (int e = 0; e < EPL; ++e) xp[e] = M<T>::fma_(x[e], c, nu[e] * s);
     return wave_sum(ess_lane_loglik<T, EPL, FULL>(xp, yv, lane, D, target, inv2v));
+}
+
+// EssLin of (x, nu) when the job's likelihood uses it (FP32 logistic).
+template <typename T, int EPL, bool FULL>
+__device__ __forceinline__ EssLin ess_lin_of(const T (&x)[EPL], const T (&nu)[EPL], const T (&yv)[EPL], int lane,
+                                             int D, int target)
+{
+    if constexpr (sizeof(T) == 4)
+        if (target == FSMMC_GP_LOGISTIC) return ess_lin<EPL, FULL>(x, nu, yv, lane, D);
+    return EssLin{0.0f, 0.0f, 0.0f, 0.0f};
 }
 
 // INIT: the slice level log y = log L(x) + log u, kept as log u, and the
@@ -515,9 +573,12 @@ struct EssTally {
 // window [t0, t0 + W), reached n draws, or spent its step budget.  Returns
 // the number of draws it emitted; the counter contributions go to tl (the
 // caller adds them to the job's counters).
-template <typename T, int EPL, bool FULL>
+// TG >= 0: the target kind fixed at compile time (the loop then holds one
+// likelihood form and its registers only); TG < 0: a.target.
+template <typename T, int EPL, bool FULL, int TG = -1>
 __device__ __forceinline__ uint32_t ess_window_run(const EssK<T>& a, int j, int lane, EssTally& tl)
 {
+    const int target = TG >= 0 ? TG : a.target;
     j = uni(j);
     uint32_t t = uni(a.t[j]);
     if (t >= (uint32_t)a.n) return 0;
@@ -538,12 +599,14 @@ __device__ __forceinline__ uint32_t ess_window_run(const EssK<T>& a, int j, int 
     unsigned long long steps = 0;
     int guards = 0;
     bool have_nu = false;
+    EssLin L{0.0f, 0.0f, 0.0f, 0.0f};
     while (t < wend && budget > 0) {
         if (!have_nu) {
             const T* nj = a.nu + ((size_t)j * a.W + (t - t0)) * a.Dp;
 #pragma unroll
             for (int e = 0; e < EPL; ++e) nu[e] = nj[e * 64 + lane];
             have_nu = true;
+            L = ess_lin_of<T, EPL, FULL>(x, nu, yv, lane, a.D, target);
         }
         if (k == 1) {
             ess_begin<T>(a.seed, (uint32_t)j, t, logu, theta, tmin, tmax);
@@ -551,7 +614,7 @@ __device__ __forceinline__ uint32_t ess_window_run(const EssK<T>& a, int j, int 
         } else {
             ess_shrink<T>(a.seed, (uint32_t)j, t, evals, theta, tmin, tmax);
         }
-        const T lp = uni(ess_propose_eval<T, EPL, FULL>(x, nu, xp, yv, theta, lane, a.D, a.target, a.inv2v));
+        const T lp = uni(ess_propose_eval<T, EPL, FULL>(x, nu, xp, yv, theta, lane, a.D, target, a.inv2v, L));
         ++evals;
         ++steps;
         --budget;
