@@ -210,8 +210,9 @@ def test_batch_ownership_and_errors(F, ctx):
             with pytest.raises(F.FsmmcError) as e:
                 F.Batch(ctx, jobs[:1])
             assert e.value.status == F.EBUSY
+            done = torch.zeros(1, dtype=torch.int32, device="cuda")
             for call in (lambda: jobs[0].step_fsm(0), lambda: jobs[1].step_synchronized(1),
-                         lambda: F.fsmmc_job_free(jobs[0].handle)):
+                         lambda: jobs[0].step_fsm_async(0, done), lambda: F.fsmmc_job_free(jobs[0].handle)):
                 with pytest.raises(F.FsmmcError) as e:
                     call()
                 assert e.value.status == F.EBUSY
