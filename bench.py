@@ -986,6 +986,9 @@ def main():
                                       batch.get("_check") if batch else None, threads)
         log("oracle checks: %s" % json.dumps(cpu["checks"]))
 
+    if ceilings and nuts:
+        gr = nuts["gradient"]["roofline"]
+        gr["frac_of_measured_peak"] = gr["achieved"] / (ceilings["measured"]["mfma_bf16_tflops"] / PIECE_PRODUCTS)
     ess.pop("_moments", None)
     ess.pop("_sample", None)
     if nuts:
