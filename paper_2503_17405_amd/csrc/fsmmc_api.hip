@@ -588,18 +588,20 @@ fsmmc_status fsmmc_init_chains(fsmmc_ctx* ctx, const fsmmc_target_spec* target,
         d.Dp = 64 * d.EPL;
         const size_t Dp = (size_t)d.Dp;
         d.N = target->n_data;
-        // Row slices of the gradient: about 512 (128-chain tile, slice) blocks at
-        // full load -- two rounds of the blocks the chip holds at once -- with
-        // slices of up to 1280 rows, a multiple of the 32-row chunk (measured
-        // with the FP32 tile at N = 10^4, m = 8192: 8 slices of 1280 rows beat 20
-        // of 512 by 5%, 5 of 2048 lose 9%).  Slices go below 256 rows only while
+        // Row slices of the gradient: about 256 (128-chain tile, slice) blocks at
+        // full load -- one round of the blocks the chip holds at once (one per
+        // CU) -- with slices of up to 1280 rows, a multiple of the 32-row chunk
+        // (N = 10^4: at 4096 chains 8 slices of 1280 rows run the NUTS job 7%
+        // faster than 16 of 640; at 8192 chains 4 slices of 2528 rows match 8
+        // of 1280 in the FSM runtime but slow the compacted baseline's partial
+        // steps by 40%, so the cap stays at 1280).  Slices go below 256 rows only while
         // the partial sums the transition adds stay within 2^20 floats per step:
         // a job of few chains then spreads its rows over many blocks instead of
         // walking them chunk after chunk in a handful (16 chains, N = 1000: 32
         // blocks of one chunk instead of 4 of eight).
         {
             const int tiles = (m + 127) / 128;
-            const int want = std::max(1, (512 + tiles - 1) / tiles);
+            const int want = std::max(1, (256 + tiles - 1) / tiles);
             const int rows = ((d.N + want - 1) / want + 31) / 32 * 32;
             const int cap = std::max(1, (1 << 20) / ((int)m * (int)Dp));
             const int rows_min = std::min(256, std::max(32, ((d.N + cap - 1) / cap + 31) / 32 * 32));
