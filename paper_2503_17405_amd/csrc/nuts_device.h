@@ -378,12 +378,13 @@ template <int EPL, class Grad>
 __device__ __forceinline__ int nuts_chain_step(const NutsK& a, const Grad& grad, int c, int lane)
 {
     c = uni(c);
-    const uint32_t t = uni(a.t[c]);
-    if (t >= a.tstop) {
+    // the draw counter and the rest of the chain's scalars in one round of
+    // loads (a finished chain reads them for nothing; they are only a few words)
+    NutsScal S = nuts_load(a, c, uni(a.t[c]));
+    if (S.t >= a.tstop) {
         if (lane == 0) a.req[c] = 0;
         return 0;
     }
-    NutsScal S = nuts_load(a, c, t);
     const int bits = nuts_chain_body<EPL>(a, grad, c, lane, S);
     nuts_store(a, c, S, (bits & NC_REQ) ? 1 : 0, lane);
     return bits & (NC_ALIVE | NC_INDRAW);
