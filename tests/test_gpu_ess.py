@@ -181,8 +181,10 @@ def test_ess_c2_full_size_sampled_chains_oracle_parity(F, ctx):
     assert r["parted"] <= 2
 
 
-@pytest.mark.parametrize("D", [1, 17, 100, 333, 700, 769, 1000])
+@pytest.mark.parametrize("D", [1, 17, 64, 100, 128, 333, 700, 769, 1000])
 def test_ess_ragged_dims_oracle_parity(F, ctx, D):
+    # 64 and 128 fill the lanes (the mask-free kernels at one and two
+    # elements per lane); the others leave a ragged last element
     w = inputs.gp_logistic(dim=D, lengthscale=0.1, jitter=1e-5, seed=D)
     m, n = 37, 40
     S, C, _ = gpu_ess(F, ctx, w, m, n, 9)
