@@ -108,27 +108,54 @@ __device__ __forceinline__ void nuts_store(const NutsK& a, int c, const NutsScal
 // Logistic regression: the gradient of the pending leapfrog arrives as
 // row-slice partials, added in slice order:
 //   grad U = theta - sum_s X_s^T r_s,  U = |theta|^2 / 2 - sum_s loglik_s.
+// The slice sums sum_s X_s^T r_s (into gs) and sum_s loglik_s (returned).
+template <int EPL>
+__device__ __forceinline__ float slice_sums(const NutsK& a, int c, int lane, WaveVec<EPL>& gs)
+{
+    float ll = 0.0f;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) gs.r[e] = 0.0f;
+    // unrolled so that the loads of several slices are in flight at once
+    // (the additions keep their order)
+#pragma unroll 8
+    for (int s = 0; s < a.nslices; ++s) {
+        const float* gp = a.Gpart + ((size_t)s * a.m + c) * a.Dp;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) gs.r[e] += gp[e * 64 + lane];
+        ll += a.Upart[(size_t)s * a.m + c];
+    }
+    return ll;
+}
+
+template <int EPL>
+__device__ __forceinline__ void slice_finish(const WaveVec<EPL>& th, const WaveVec<EPL>& gs, float ll,
+                                             WaveVec<EPL>& g, float& U)
+{
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) g.r[e] = th.r[e] - gs.r[e];
+    U = uni(0.5f * wdot(th, th) - ll);
+}
+
 struct SliceGrad {
     const NutsK& a;
     template <int EPL>
     __device__ __forceinline__ void operator()(int c, const WaveVec<EPL>& th, int lane, WaveVec<EPL>& g,
                                                float& U) const
     {
-        float ll = 0.0f;
-#pragma unroll
-        for (int e = 0; e < EPL; ++e) g.r[e] = 0.0f;
-        // unrolled so that the loads of several slices are in flight at once
-        // (the additions keep their order)
-#pragma unroll 8
-        for (int s = 0; s < a.nslices; ++s) {
-            const float* gp = a.Gpart + ((size_t)s * a.m + c) * a.Dp;
-#pragma unroll
-            for (int e = 0; e < EPL; ++e) g.r[e] += gp[e * 64 + lane];
-            ll += a.Upart[(size_t)s * a.m + c];
-        }
-#pragma unroll
-        for (int e = 0; e < EPL; ++e) g.r[e] = th.r[e] - g.r[e];
-        U = uni(0.5f * wdot(th, th) - ll);
+        WaveVec<EPL> gs;
+        const float ll = slice_sums<EPL>(a, c, lane, gs);
+        slice_finish<EPL>(th, gs, ll, g, U);
+    }
+};
+
+// The same with the slice sums formed ahead (one chain's).
+template <int EPL>
+struct PreSliceGrad {
+    const WaveVec<EPL>& gs;
+    float ll;
+    __device__ __forceinline__ void operator()(int, const WaveVec<EPL>& th, int, WaveVec<EPL>& g, float& U) const
+    {
+        slice_finish<EPL>(th, gs, ll, g, U);
     }
 };
 
@@ -143,8 +170,17 @@ __device__ __forceinline__ float nuts_leaf_accept(float w)
 // The step on a chain's registers: finish the pending leapfrog with the
 // gradient `grad` supplies at its new position, then run the cheap states
 // until the next request.  Returns NutsChainBits.
-template <int EPL, class Grad>
-__device__ __forceinline__ int nuts_chain_body(const NutsK& a, const Grad& grad, int c, int lane, NutsScal& S)
+// The vectors a pending leapfrog reads (half-step momentum, new position,
+// rho of the subtree), loaded before the chain's scalars arrive: in the FSM
+// runtime a live chain has a leapfrog pending at every step but its first.
+template <int EPL>
+struct NutsPre {
+    WaveVec<EPL> ph, th, rs;
+};
+
+template <int EPL, class Grad, bool PRE = false>
+__device__ __forceinline__ int nuts_chain_body(const NutsK& a, const Grad& grad, int c, int lane, NutsScal& S,
+                                               const NutsPre<EPL>* pre = nullptr)
 {
     float* Vc = a.V + (size_t)c * a.nvec * a.Dp;
     auto vec = [&](int i) { return Vc + (size_t)i * a.Dp; };
@@ -168,9 +204,15 @@ __device__ __forceinline__ int nuts_chain_body(const NutsK& a, const Grad& grad,
         const float vhe = (float)v * he;
         // independent loads issued together: half-step momentum, new edge position, rho_sub
         WaveVec<EPL> g, p, ph, th, rs;
-        ph.load(vec(V_PH), lane);
-        th.load(vec(eth), lane);
-        rs.load(vec(V_RHOS), lane);
+        if constexpr (PRE) {
+            ph = pre->ph;
+            th = pre->th;  // the request buffer holds the new edge position too
+            rs = pre->rs;
+        } else {
+            ph.load(vec(V_PH), lane);
+            th.load(vec(eth), lane);
+            rs.load(vec(V_RHOS), lane);
+        }
         float Un;
         grad(c, th, lane, g, Un);
 #pragma unroll
@@ -390,11 +432,31 @@ __device__ __forceinline__ int nuts_chain_step(const NutsK& a, const Grad& grad,
     return bits & (NC_ALIVE | NC_INDRAW);
 }
 
-// Logistic regression (gradient from the row-slice partials).
+// Logistic regression (gradient from the row-slice partials).  FSM runtime:
+// the pending leapfrog's vectors and slice sums are loaded in the same round
+// as the chain's scalars (a chain that turns out finished or not pending
+// read them for nothing; the synchronized runtimes, whose waiting chains are
+// not pending, load after the scalars).
 template <int EPL>
 __device__ __forceinline__ int nuts_chain_step(const NutsK& a, int c, int lane)
 {
-    return nuts_chain_step<EPL>(a, SliceGrad{a}, c, lane);
+    if (a.mode != 0) return nuts_chain_step<EPL>(a, SliceGrad{a}, c, lane);
+    c = uni(c);
+    const float* Vc = a.V + (size_t)c * a.nvec * a.Dp;
+    NutsPre<EPL> P;
+    P.ph.load(Vc + (size_t)V_PH * a.Dp, lane);
+    P.th.load(a.Thq + (size_t)c * a.Dp, lane);
+    P.rs.load(Vc + (size_t)V_RHOS * a.Dp, lane);
+    WaveVec<EPL> gs;
+    const float ll = slice_sums<EPL>(a, c, lane, gs);
+    NutsScal S = nuts_load(a, c, uni(a.t[c]));
+    if (S.t >= a.tstop) {
+        if (lane == 0) a.req[c] = 0;
+        return 0;
+    }
+    const int bits = nuts_chain_body<EPL, PreSliceGrad<EPL>, true>(a, PreSliceGrad<EPL>{gs, ll}, c, lane, S, &P);
+    nuts_store(a, c, S, (bits & NC_REQ) ? 1 : 0, lane);
+    return bits & (NC_ALIVE | NC_INDRAW);
 }
 
 // Chains of one job that asked for a gradient, in chain order (one block of
